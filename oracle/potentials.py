@@ -1,0 +1,95 @@
+"""Classical pair potentials (oracle; test infrastructure only).
+
+The paper lists Lennard-Jones, Morse and soft-sphere among the classical potentials the engine
+supports (Abstract) without writing them down; these are the textbook forms.
+
+Per species pair the parameter triple p = params[s_i, s_j] is
+    LJ           (epsilon, sigma, unused)     phi = 4 eps [(sigma/r)^12 - (sigma/r)^6]
+    Morse        (D, alpha, r0)               phi = D [exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0))]
+    soft sphere  (epsilon, sigma_ij, unused)  phi = (eps / 2) (1 - r / sigma_ij)^2   for r < sigma_ij
+A pair interacts when r < r_c (and, for the soft sphere, also r < sigma_ij).  With the energy
+shift, phi(r) - phi(r_c) is used inside the cutoff (forces unchanged).
+
+Every function takes arrays of r and of parameter triples (one per pair) and returns float64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+KINDS = ("lj", "morse", "soft_sphere")
+
+
+def phi_and_derivs(kind: str, p: np.ndarray, r: np.ndarray):
+    """phi(r), phi'(r), phi''(r) for parameter rows p (P, 3) and distances r (P,)."""
+    r = np.asarray(r, dtype=np.float64)
+    if kind == "lj":
+        eps, sig = p[:, 0], p[:, 1]
+        sr6 = (sig / r) ** 6
+        sr12 = sr6 * sr6
+        phi = 4.0 * eps * (sr12 - sr6)
+        d1 = 24.0 * eps / r * (sr6 - 2.0 * sr12)
+        d2 = 4.0 * eps / (r * r) * (156.0 * sr12 - 42.0 * sr6)
+    elif kind == "morse":
+        D, alpha, r0 = p[:, 0], p[:, 1], p[:, 2]
+        x = np.exp(-alpha * (r - r0))
+        phi = D * (x * x - 2.0 * x)
+        d1 = 2.0 * alpha * D * (x - x * x)
+        d2 = 2.0 * alpha * alpha * D * (2.0 * x * x - x)
+    elif kind == "soft_sphere":
+        eps, sig = p[:, 0], p[:, 1]
+        u = 1.0 - r / sig
+        phi = 0.5 * eps * u * u
+        d1 = -eps / sig * u
+        d2 = eps / (sig * sig) * np.ones_like(r)
+    else:
+        raise ValueError(kind)
+    return phi, d1, d2
+
+
+def in_range(kind: str, p: np.ndarray, r2: np.ndarray, cutoff: float) -> np.ndarray:
+    """Interaction mask, decided in float64 on squared distances: r^2 < r_c^2 (and r^2 < sigma_ij^2
+    for the soft sphere)."""
+    m = r2 < cutoff * cutoff
+    if kind == "soft_sphere":
+        m &= r2 < p[:, 1] * p[:, 1]
+    return m
+
+
+def energy_shift(kind: str, p: np.ndarray, cutoff: float, shift: bool) -> np.ndarray:
+    """phi(r_c) per parameter row when the energy is shifted, else zeros (soft sphere: zero)."""
+    if not shift or kind == "soft_sphere":
+        return np.zeros(p.shape[0])
+    return phi_and_derivs(kind, p, np.full(p.shape[0], cutoff))[0]
+
+
+def dg_dparams(kind: str, p: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Derivatives of g(r) = phi'(r) / r with respect to the three parameter slots, shape (P, 3).
+    The pair force on i is g(r) d, so these give the pair-force parameter derivatives."""
+    r = np.asarray(r, dtype=np.float64)
+    out = np.zeros((r.shape[0], 3))
+    if kind == "lj":
+        eps, sig = p[:, 0], p[:, 1]
+        sr6 = (sig / r) ** 6
+        sr12 = sr6 * sr6
+        g = 24.0 * eps / (r * r) * (sr6 - 2.0 * sr12)
+        out[:, 0] = g / eps
+        # d/dsigma of sr6 = 6 sr6 / sigma, of sr12 = 12 sr12 / sigma
+        out[:, 1] = 24.0 * eps / (r * r) * (6.0 * sr6 - 24.0 * sr12) / sig
+    elif kind == "morse":
+        D, alpha, r0 = p[:, 0], p[:, 1], p[:, 2]
+        x = np.exp(-alpha * (r - r0))
+        d1 = 2.0 * alpha * D * (x - x * x)
+        out[:, 0] = d1 / D / r
+        dx_da = -(r - r0) * x
+        out[:, 1] = (2.0 * D * (x - x * x) + 2.0 * alpha * D * (1.0 - 2.0 * x) * dx_da) / r
+        dx_dr0 = alpha * x
+        out[:, 2] = 2.0 * alpha * D * (1.0 - 2.0 * x) * dx_dr0 / r
+    elif kind == "soft_sphere":
+        eps, sig = p[:, 0], p[:, 1]
+        u = 1.0 - r / sig
+        out[:, 0] = -u / sig / r
+        # phi' = -eps/sig + eps r / sig^2  ->  d/dsig = eps/sig^2 - 2 eps r / sig^3
+        out[:, 1] = (eps / (sig * sig) - 2.0 * eps * r / sig ** 3) / r
+    else:
+        raise ValueError(kind)
+    return out

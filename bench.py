@@ -1,0 +1,220 @@
+"""Benchmark: batched Lennard-Jones argon NVE, 64 systems x 864 atoms, on one MI355X.
+
+One step = one velocity-Verlet step of the whole batch (device-side neighbor validity test and
+rebuilds included), FP32 pair arithmetic with FP64 integration, the step loop replayed from
+hipGraphs.  Prints one JSON line with atom-steps/s, the force kernel's roofline position, the
+plain one-system-per-launch path on the same GPU, the adjoint (trajectory-gradient) throughput
+of the 16 x 864 differentiable run, and the FP64 CPU oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--chunk C] [--no-plain] [--no-adjoint] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s batched LJ NVE (64×864 atoms) + adjoint steps/s, vs plain path"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor):
+    pot = w.potential
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
+    pp = api.pair_params_from_spec(pot, w.pair_prec)
+    F = api.force_buffer(b, w.pair_prec)
+    api.ts_pair_forces(b, nl, pp, F)
+    chunk = max(1, min(chunk, steps))
+    n_full, rest = divmod(steps, chunk)
+    w_runs = max(1, -(-warmup // chunk)) if warmup > 0 else 0
+    for _ in range(w_runs):
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, chunk, F, use_graph=True)
+    if rest:
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, rest, F, use_graph=True)  # instantiate its graph
+    torch.cuda.synchronize()
+    nl.status.zero_()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(n_full):
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, chunk, F, use_graph=True)
+    if rest:
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, rest, F, use_graph=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    st = nl.read_status()
+    if st[1] or st[3] or st[4]:
+        raise RuntimeError(f"neighbor list status after the timed run: {st.tolist()}")
+    return dict(ms=ms, wall_s=wall, warmup_steps=w_runs * chunk + rest, rebuilds=int(st[2]),
+                max_nbr=int(st[0]), capacity=nl.max_nbr, batch=b, nl=nl, pp=pp, F=F)
+
+
+def force_kernel_roofline(api, torch, r, reps=200):
+    """Average duration of the pair-force kernel alone (the NVE loop's variant: forces only),
+    timed with events on the stream it is launched on, and its algorithmic HBM bytes."""
+    b, nl, pp, F = r["batch"], r["nl"], r["pp"], r["F"]
+    for _ in range(10):
+        api.ts_pair_forces(b, nl, pp, F)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.ts_pair_forces(b, nl, pp, F)
+    e1.record()
+    torch.cuda.synchronize()
+    avg_ms = e0.elapsed_time(e1) / reps
+    n = b.n_atoms
+    entries = int(nl.n_nbr.sum().item())
+    fbytes = 4 if F.dtype == torch.float32 else 8
+    # per atom: position 24 B, list length 4 B, system index 4 B, force 3*fbytes; per entry 4 B
+    alg = n * (24 + 4 + 4 + 3 * fbytes) + 4 * entries
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="k_pair_forces<LJ,float,EV=0>",
+                avg_launch_us=round(avg_ms * 1e3, 3), alg_bytes_per_launch=alg,
+                alg_bytes_per_atom=round(alg / n, 1), mean_list_len=round(entries / n, 2))
+
+
+def plain_path(api, torch, w, steps, bin_factor):
+    """Same kernels, one system per launch sequence, no graph: systems advanced one after another."""
+    pot = w.potential
+    pp = api.pair_params_from_spec(pot, w.pair_prec)
+    runs = []
+    for s in range(w.n_systems):
+        ws = w.subset([s])
+        b = api.Batch.from_workload(ws)
+        nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
+        F = api.force_buffer(b, w.pair_prec)
+        api.ts_pair_forces(b, nl, pp, F)
+        runs.append((b, nl, F))
+    for b, nl, F in runs:  # warm-up
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, 2, F, use_graph=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, nl, F in runs:
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, steps, F, use_graph=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(value=w.n_atoms * steps / dt, steps=steps, seconds=round(dt, 4))
+
+
+def adjoint_throughput(api, torch, n_systems, n_steps, checkpoint):
+    from paper_2508_06628_amd.trajectory import TrajectoryRDF
+    from workloads import argon_adjoint_batch
+    w = argon_adjoint_batch(n_systems, n_steps=n_steps)
+    eng = TrajectoryRDF(w, n_steps, checkpoint, prec="f32")
+    pos0 = eng.batch.pos.clone()
+    eps, sig = float(w.potential.params[0, 0, 0]), float(w.potential.params[0, 0, 1])
+    g_t = eng.run(eps * 1.05, sig * 1.05, pos0).clone()
+    eng.set_target(g_t)
+    eng.forward(eps, sig, pos0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eng.forward(eps, sig, pos0)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    de, ds, dr = eng.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    return dict(value=w.n_atoms * n_steps / t_bwd, unit="atom-steps/s (backward: recompute + reverse)",
+                workload=f"argon_adjoint_{n_systems}x864_{n_steps}steps_ckpt{checkpoint}",
+                steps_per_s=round(n_steps / t_bwd, 2), backward_s=round(t_bwd, 3), forward_s=round(t_fwd, 3),
+                loss=float(eng.loss.item()), dL_deps=de, dL_dsigma=ds)
+
+
+def cpu_baseline(w, steps=2):
+    """The FP64 oracle (brute-force pair search) on one system of the workload, on the host."""
+    from oracle import integrate
+    ws = w.subset([0])
+    t0 = time.perf_counter()
+    integrate.nve(ws.pos, ws.vel, ws.mass, ws.cell, ws.sys_offsets, ws.species, ws.potential, ws.dt, steps, ws.accel)
+    dt = time.perf_counter() - t0
+    return dict(value=round(ws.n_atoms * steps / dt, 2), unit="atom-steps/s", cores=1, kind="oracle",
+                sample=f"1 system x {ws.n_atoms} atoms, {steps} NVE steps (+1 initial force evaluation), "
+                       f"{dt:.1f} s, single process float64 NumPy")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=15)
+    ap.add_argument("--chunk", type=int, default=100)
+    ap.add_argument("--bin-factor", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=500)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (systems would shard "
+              "across GPUs by bin packing; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2508_06628_amd import api
+    from workloads import argon_batch
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    w = argon_batch(64, seed=1, n_steps=args.steps)
+    log(f"workload {w.name}: {w.n_systems} systems, {w.n_atoms} atoms")
+    r = batched_nve(api, torch, w, args.steps, args.warmup, args.chunk, args.bin_factor)
+    ms_per_step = r["ms"] / args.steps
+    value = w.n_atoms * args.steps / (r["ms"] * 1e-3)
+    log(f"batched NVE: {ms_per_step * 1e3:.2f} us/step, {value:.4g} atom-steps/s, rebuilds {r['rebuilds']}")
+    roof = force_kernel_roofline(api, torch, r)
+    log(f"force kernel: {roof['avg_launch_us']} us/launch, {roof['achieved']} GB/s algorithmic")
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": r["warmup_steps"],
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair / f64 integration",
+        "data": "synthetic",
+        "config": {"workload": "argon_lj_nve_64x864", "n_systems": w.n_systems, "atoms_per_system": 864,
+                   "n_atoms": w.n_atoms, "dt_fs": w.dt, "skin_A": w.skin, "cutoff_A": w.potential.cutoff,
+                   "pair_prec": w.pair_prec, "graph_chunk_steps": args.chunk, "bin_factor": args.bin_factor,
+                   "list_capacity": r["capacity"], "max_list_len": r["max_nbr"], "system_rebuilds": r["rebuilds"],
+                   "wall_s": round(r["wall_s"], 4)},
+        "roofline": roof,
+    }
+    if not args.no_plain:
+        p = plain_path(api, torch, w, args.plain_steps, args.bin_factor)
+        p["speedup_batched_vs_plain"] = round(value / p["value"], 2)
+        out["plain_path"] = p
+        log(f"plain path: {p['value']:.4g} atom-steps/s")
+    if not args.no_adjoint:
+        a = adjoint_throughput(api, torch, 16, args.adjoint_steps, 50)
+        out["adjoint"] = a
+        log(f"adjoint: {a['value']:.4g} atom-steps/s")
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+        log(f"cpu oracle: {out['cpu_baseline']['value']} atom-steps/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,254 @@
+/*
+ * ts_api.h -- C ABI of the MI355X (gfx950) batched pair-potential simulation library.
+ *
+ * The library advances many periodic systems of uneven size together, as the paper's batched
+ * state does (TorchSim, arXiv 2508.06628, Section 3: atom-wise attributes concatenated,
+ * system-wise attributes stacked).  It implements the classical pair-potential hot path:
+ * cell-list neighbor build under triclinic periodic boundaries, Lennard-Jones / Morse /
+ * soft-sphere energy, forces and virial (the model output schema of energies, forces and
+ * stress, Section 2), velocity-Verlet NVE and FIRE relaxation (the integrators and relaxation
+ * optimizers of the Abstract), and the adjoint of the pair step and the integrator used to
+ * differentiate a trajectory observable (differentiable simulation, Section 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array pointer inside the structs below is a DEVICE pointer (memory from hipMalloc,
+ *   e.g. a torch tensor's data_ptr) owned by the caller, unless the field says "host".
+ *   The library never frees caller memory and never allocates inside a ts_* call, except
+ *   for the hipGraph objects ts_nve_step keeps in its replay cache (see there).
+ * - Positions, velocities, forces and adjoints are structure-of-arrays: component c of atom i
+ *   is at p[c * stride + i], 0 <= i < n_atoms (stride >= n_atoms; 0 means n_atoms).
+ * - cell is [S][3][3] row-major with row a = lattice vector a; Cartesian = fractional @ cell.
+ *   The pair vector of the periodic image S in Z^3 is d = r_j - r_i + S @ cell.  Positions are
+ *   never wrapped: whole lattice vectors by which a position sits outside its cell go into S.
+ * - Atoms of system s are the contiguous range [sys_offsets[s], sys_offsets[s+1]).
+ * - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default stream).  The
+ *   return value reports only synchronous argument errors, checked before any launch.
+ *   Conditions found while kernels run (neighbor-list overflow, non-finite positions,
+ *   image-shift overflow) are written to the caller-owned device status words of the neighbor
+ *   list, which the caller reads at a synchronisation point.  No exception crosses the ABI.
+ * - Calls on one stream are ordered; calls that share output buffers on different streams race.
+ */
+#ifndef TS_API_H
+#define TS_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *ts_stream_t; /* hipStream_t */
+
+typedef enum {
+  TS_OK = 0,
+  TS_NOT_CONVERGED = 1,
+  TS_E_INVALID = -1,     /* bad argument (null pointer, inconsistent sizes, singular cell ...) */
+  TS_E_UNSUPPORTED = -2, /* valid but outside what this build implements */
+  TS_E_CAPACITY = -3,    /* a size exceeds a documented limit of the library */
+  TS_E_HIP = -4          /* the HIP runtime reported an error (launch, graph, device query) */
+} ts_status;
+
+typedef enum { TS_LJ = 0, TS_MORSE = 1, TS_SOFT_SPHERE = 2 } ts_potential;
+typedef enum { TS_PAIR_F32 = 0, TS_PAIR_F64 = 1 } ts_pair_prec;
+
+#define TS_MAX_SPECIES 4
+#define TS_MAX_SYSTEM_ATOMS 131072 /* atoms per system: 17-bit local index in a list entry */
+#define TS_MAX_IMAGE_SHIFT 15      /* |S_k| per pair: 5-bit field in a list entry */
+
+/* Neighbor-list status words (device int64[TS_STATUS_WORDS]); cumulative until the caller clears
+   them (e.g. with a fill kernel or torch.zero_()). */
+#define TS_STATUS_MAX_NBR 0   /* largest per-atom neighbor count found by any build (atomic max) */
+#define TS_STATUS_OVERFLOW 1  /* 1 if some atom had more neighbors than max_nbr (list truncated) */
+#define TS_STATUS_REBUILDS 2  /* number of system rebuilds performed */
+#define TS_STATUS_NONFINITE 3 /* 1 if a build met a non-finite position or a singular cell */
+#define TS_STATUS_SHIFT 4     /* 1 if an image shift fell outside [-15, 15] (entry dropped) */
+#define TS_STATUS_WORDS 8
+
+/* Batched state (paper Section 3: concatenated atom-wise, stacked system-wise attributes). */
+typedef struct {
+  int64_t n_atoms;              /* N: total atoms of all systems */
+  int64_t n_systems;            /* S */
+  int64_t stride;               /* leading dimension of the SoA arrays (0 = n_atoms) */
+  const int64_t *sys_offsets;   /* device [S+1], nondecreasing, sys_offsets[0] = 0, [S] = N */
+  const int64_t *h_sys_offsets; /* HOST copy of sys_offsets (launch planning and validation) */
+  const int32_t *system_idx;    /* device [N]: system of each atom, consistent with sys_offsets */
+  double *pos;                  /* device SoA [3][stride] float64 */
+  double *vel;                  /* device SoA [3][stride] float64 (may be NULL for ts_pair_forces) */
+  const double *mass;           /* device [N] float64; NULL = unit masses */
+  const int32_t *species;       /* device [N] int32 in [0, n_species); NULL = all species 0 */
+  double *cell;                 /* device [S][3][3] float64 */
+} ts_batch;
+
+/* Pair potential (paper Abstract: Lennard-Jones, Morse, soft-sphere).  Host struct, passed by
+   pointer and copied at launch.  params[si][sj] holds
+     TS_LJ:          (epsilon, sigma, unused)   phi = 4 eps ((sigma/r)^12 - (sigma/r)^6)
+     TS_MORSE:       (D, alpha, r0)             phi = D (exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0)))
+     TS_SOFT_SPHERE: (epsilon, sigma_ij, unused) phi = eps/2 (1 - r/sigma_ij)^2 for r < sigma_ij
+   A pair interacts when r^2 < cutoff^2 (decided in float64), and for the soft sphere also
+   r^2 < sigma_ij^2.  shift_energy = 1 subtracts phi(cutoff) inside the cutoff (LJ, Morse).
+   prec = TS_PAIR_F32: the pair vector and the cutoff test are float64, the pair function is
+   evaluated in float32 (soft sphere: overlap 1 - r/sigma_ij in float64), and forces, energies,
+   virials are accumulated in float64; forces are stored as float32.  TS_PAIR_F64: all float64. */
+typedef struct {
+  int32_t kind;         /* ts_potential */
+  int32_t prec;         /* ts_pair_prec */
+  int32_t n_species;    /* 1..TS_MAX_SPECIES */
+  int32_t shift_energy; /* 0 or 1 */
+  double cutoff;        /* r_c > 0 */
+  double params[TS_MAX_SPECIES][TS_MAX_SPECIES][3];
+} ts_pair_params;
+
+/* Neighbor list: padded per-atom rows.  Entry k of atom i is nbr[k * stride + i] for
+   k < n_nbr[i] <= max_nbr, packed as  j_local | (S0+16) << 17 | (S1+16) << 22 | (S2+16) << 27
+   with j_local = j - sys_offsets[system of i] (so each system may hold up to 2^17 atoms).
+   A list built at (ref_pos, ref_cell) with list radius r_list = cutoff + skin holds every (j, S)
+   with |d| < r_list (float64 test), j != i or S != 0, and stays valid while
+   2 max_i |r_i - ref_i M| + r_list ||M - I||_F <= skin, M = ref_cell^-1 cell (M = I when the
+   cell is bitwise unchanged); a system is rebuilt as soon as that bound is exceeded. */
+typedef struct {
+  double cutoff;       /* r_c of the consumer (pair potential cutoff, or the RDF range) */
+  double skin;         /* >= 0 */
+  int32_t half;        /* 0 = full list (each pair from both sides).  1 = half list (i<j, or
+                          i==j with S lexicographically positive); the force, NVE, FIRE and
+                          adjoint entry points require half = 0 */
+  int32_t max_nbr;     /* per-atom capacity (rows of nbr) */
+  int32_t bin_factor;  /* cell-list bins per list radius along each direction (1..4) */
+  int32_t reserved;
+  int32_t *nbr;        /* device [max_nbr][stride] */
+  int32_t *n_nbr;      /* device [N] */
+  double *ref_pos;     /* device SoA [3][stride]: positions at the last build of each system */
+  double *ref_cell;    /* device [S][9]: cell at the last build */
+  int64_t *status;     /* device int64[TS_STATUS_WORDS] */
+  void *workspace;     /* device, ts_neighbor_workspace_bytes(N, S) bytes, caller-owned */
+  size_t workspace_bytes;
+} ts_neighbor_list;
+
+/* Bytes of device workspace a neighbor list needs for N atoms in S systems. */
+size_t ts_neighbor_workspace_bytes(int64_t n_atoms, int64_t n_systems);
+
+/* Build (force = 1) or update (force = 0) the neighbor list of every system.  With force = 0 a
+   system is rebuilt only when the validity bound above is exceeded for it; the test and the
+   rebuild both run on the device (no host synchronisation).  Binning: fractional coordinates
+   s = r cell^-1 (float64) wrapped to [0, 1); n_k = max(1, floor(bin_factor w_k / r_list)) bins
+   along direction k (w_k the perpendicular width), reduced until a system has at most 2 N_s + 1
+   bins; every bin within reach (stencil ceil(r_list n_k / w_k), several images of one bin when
+   the cell is narrower than 2 r_list) is searched.  Entries of a row are ordered by stencil
+   position then atom index, so a list is a deterministic function of positions and cells.
+   Errors: TS_E_INVALID (null pointers, sizes, cutoff <= 0, skin < 0, max_nbr < 1,
+   workspace too small), TS_E_CAPACITY (a system above TS_MAX_SYSTEM_ATOMS). */
+int ts_neighbor_build(const ts_batch *batch, ts_neighbor_list *nl, int32_t force, ts_stream_t stream);
+
+/* Energy per system, force per atom and virial per system from the pair potential:
+     E_s = 1/2 sum_{(i,j,S)} [phi(r) - shift],  F_i = sum_{(j,S)} (phi'(r)/r) d,
+     W_s = -1/2 sum_{(i,j,S)} (phi'(r)/r) d (x) d  (stress = -W/V).
+   force: SoA [3][stride], float32 when prec = TS_PAIR_F32, float64 when TS_PAIR_F64 (overwritten).
+   energy [S] and virial [S][9] (float64) are overwritten; either may be NULL to skip it.
+   The list must be valid for the batch's positions (build it first).
+   Errors: TS_E_INVALID, TS_E_UNSUPPORTED (half list, unknown kind/prec). */
+int ts_pair_forces(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp, void *force,
+                   double *energy, double *virial, ts_stream_t stream);
+
+/* n_steps of velocity-Verlet NVE on every system (kick-drift-kick, one force evaluation per step):
+     v += dt/2 a F/m;  r += dt v;  [list update];  F = F(r);  v += dt/2 a F/m
+   with a = accel (force/mass -> length/time^2; 0.009648533215665327 for eV, A, amu, fs).
+   force: in: F(r_0) valid (f32 or f64 as pp->prec); out: F(r_n).  The neighbor list is updated
+   on the device each step by the validity bound.  On return (when the stream completes)
+   epot [S], ekin [S] = 1/2 sum m v^2 / accel and virial [S][9] hold the final state's values
+   (each may be NULL).  use_graph = 1 captures the whole step loop in one hipGraph that is cached
+   (keyed by every argument) and replayed on later identical calls; the cache holds at most 16
+   graphs per process and is released by ts_release_graphs().  use_graph = 0 launches eagerly.
+   Errors: TS_E_INVALID (dt or accel not finite/positive, n_steps < 0, vel NULL ...),
+   TS_E_UNSUPPORTED, TS_E_HIP (graph capture failed). */
+int ts_nve_step(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_params *pp, double dt, double accel,
+                int32_t n_steps, void *force, double *epot, double *ekin, double *virial, int32_t use_graph,
+                ts_stream_t stream);
+
+/* FIRE relaxation (Bitzek et al., PRL 97, 170201 (2006); the paper's structural relaxation
+   optimizers, Abstract).  Per system and iteration: forces; stop if converged
+   (max_i |F_i| < fmax, and with relax_cell also max |G_ab| < fmax); from the second iteration on
+   P = g.v: P > 0 -> v = (1-alpha) v + alpha |v| g/|g|, n_pos++, and after n_min such steps
+   dt = min(f_inc dt, dt_max), alpha *= f_alpha; P <= 0 -> v = 0, dt *= f_dec, alpha = alpha_start,
+   n_pos = 0; then v += dt g/m and x += dt v (time unit: acceleration = F/m).
+   relax_cell = 1 adds the cell: r_i = q_i D, cell = ref_cell D (D_0 = I); atom coordinates q_i
+   with g_i = F_i D^T; cell coordinate Y = N_s D with force G = D^-T W / N_s and mass cell_mass;
+   zero external pressure.  Velocities of q live in batch->vel. */
+typedef struct {
+  double dt_start, dt_max, alpha_start, f_inc, f_dec, f_alpha, fmax, cell_mass;
+  int32_t n_min, relax_cell;
+  int64_t max_iter; /* per system; a system that reaches it stops with converged = 0 */
+} ts_fire_config;
+
+typedef struct {
+  double *dt;         /* device [S] */
+  double *alpha;      /* device [S] */
+  int32_t *n_pos;     /* device [S] */
+  int32_t *converged; /* device [S] */
+  int64_t *n_iter;    /* device [S]: updates performed so far */
+  double *deform;     /* device [S][9]: D (relax_cell only; may be NULL otherwise) */
+  double *deform_vel; /* device [S][9]: velocity of Y (relax_cell only) */
+  double *ref_cell;   /* device [S][9]: cell at D = I (relax_cell only) */
+  double *scratch;    /* device [S][32] float64 working space */
+} ts_fire_state;
+
+/* Advance every unconverged system by up to n_iter FIRE iterations (n_iter >= 1), then evaluate
+   forces and the convergence test at the final configuration: on completion force/energy/virial
+   (each may be NULL; force is required) describe the final positions and converged[] is current.
+   The caller initialises the state (vel = 0, dt = dt_start, alpha = alpha_start, n_pos = 0,
+   converged = 0, n_iter = 0, deform = I, deform_vel = 0, ref_cell = cell).
+   Errors: TS_E_INVALID, TS_E_UNSUPPORTED. */
+int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,
+                 const ts_pair_params *pp, int64_t n_iter, void *force, double *energy, double *virial,
+                 ts_stream_t stream);
+
+/* Adjoint of velocity-Verlet sub-steps (differentiable simulation, paper Section 2).  With
+   lr = adj_pos = dL/dr and lv = adj_vel = dL/dv (SoA float64), u = accel lv / m and J = dF/dr
+   evaluated at batch->pos:
+     lv += dt_drift lr;   lr += w_kick J u;   adj_params[si][sj][k] += w_kick sum_i u_i . dF_i/dtheta
+   where theta = params[si][sj][k] of the pair potential, accumulated per ordered species pair of
+   the full list (for a symmetric parameter the gradient is [a][b][k] + [b][a][k] when a != b).
+   Per pair: (J u)_i += phi'' (d^.du) d^ + (phi'/r)(du - (d^.du) d^), du = u_j - u_i.
+   One reverse velocity-Verlet step from (lr, lv) at step n+1 to step n is
+     (dt_drift = 0, w_kick = dt/2) at r_{n+1}, then (dt_drift = dt, w_kick = dt/2) at r_n;
+   consecutive half kicks at the same positions merge into one call with w_kick = dt.
+   adj_params is device float64 [TS_MAX_SPECIES][TS_MAX_SPECIES][3] (may be NULL).
+   Pair arithmetic follows pp->prec; every accumulator is float64. */
+int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp, double dt_drift,
+                    double w_kick, double accel, double *adj_pos, double *adj_vel, double *adj_params,
+                    ts_stream_t stream);
+
+/* Gaussian-smeared radial distribution function per system over the full pair set within r_max
+   (the list's radius must be >= r_max):
+     g_s(r_b) = sum_{(i,j,S), |d| < r_max} N(r_b - |d|; sigma) / (4 pi r_b^2 rho_s N_s),
+   r_b = (b + 1/2) r_end / n_bins, rho_s = N_s / V_s, N the normal density of std sigma.
+   g: device float64 [S][n_bins], overwritten. */
+int ts_rdf_smeared(const ts_batch *batch, const ts_neighbor_list *nl, int32_t n_bins, double r_end, double sigma,
+                   double r_max, double *g, ts_stream_t stream);
+
+/* Mean-squared RDF loss L = 1/(S n_bins) sum (g - g_target)^2 and dL/dg.  loss: device float64[1];
+   dl_dg: device [S][n_bins] (either may be NULL). */
+int ts_rdf_loss(const double *g, const double *g_target, int64_t n_systems, int32_t n_bins, double *loss,
+                double *dl_dg, ts_stream_t stream);
+
+/* Accumulate grad_pos += d(sum_{s,b} dl_dg[s][b] g_s(r_b)) / d pos (SoA float64 [3][stride]). */
+int ts_rdf_vjp(const ts_batch *batch, const ts_neighbor_list *nl, int32_t n_bins, double r_end, double sigma,
+               double r_max, const double *dl_dg, double *grad_pos, ts_stream_t stream);
+
+/* ekin[s] = 1/2 sum_{i in s} m_i |v_i|^2 / accel (float64, overwritten). */
+int ts_kinetic_energy(const ts_batch *batch, double accel, double *ekin, ts_stream_t stream);
+
+/* Release every cached hipGraph (see ts_nve_step). */
+void ts_release_graphs(void);
+
+/* Static description of a status code. */
+const char *ts_strerror(int status);
+
+/* Library version string. */
+const char *ts_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TS_API_H */

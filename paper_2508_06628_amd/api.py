@@ -1,0 +1,315 @@
+"""Python binding of the C ABI: device buffers held in torch tensors, one function per entry
+point with the entry point's name.  Every function only marshals arguments; all the work runs in
+the HIP library.  Arrays are on the current HIP device; calls are asynchronous on the current
+torch stream unless a stream is passed.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------------------------- batch
+
+
+class Batch:
+    """Batched state on the device: SoA positions/velocities [3][N] (float64), masses [N],
+    species [N] (int32), system offsets [S+1] (int64, plus a host copy), system index [N],
+    cells [S][3][3] (rows are lattice vectors)."""
+
+    def __init__(self, pos, vel, mass, species, sys_offsets, cell, device="cuda"):
+        pos = np.asarray(pos, dtype=np.float64)
+        self.h_offsets = np.ascontiguousarray(np.asarray(sys_offsets, dtype=np.int64))
+        self.n_atoms = int(pos.shape[0])
+        self.n_systems = int(self.h_offsets.shape[0] - 1)
+        self.device = torch.device(device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.pos = torch.tensor(np.ascontiguousarray(pos.T), **f64)
+        vel = np.zeros_like(pos) if vel is None else np.asarray(vel, dtype=np.float64)
+        self.vel = torch.tensor(np.ascontiguousarray(vel.T), **f64)
+        self.mass = None if mass is None else torch.tensor(np.asarray(mass, dtype=np.float64), **f64)
+        self.species = None if species is None else torch.tensor(np.asarray(species, dtype=np.int32),
+                                                                  dtype=torch.int32, device=self.device)
+        self.sys_offsets = torch.tensor(self.h_offsets, dtype=torch.int64, device=self.device)
+        counts = np.diff(self.h_offsets)
+        self.system_idx = torch.tensor(np.repeat(np.arange(self.n_systems, dtype=np.int32), counts),
+                                       dtype=torch.int32, device=self.device)
+        self.cell = torch.tensor(np.asarray(cell, dtype=np.float64).reshape(self.n_systems, 3, 3), **f64)
+
+    @classmethod
+    def from_workload(cls, w, device="cuda"):
+        return cls(w.pos, w.vel, w.mass, w.species, w.sys_offsets, w.cell, device)
+
+    @property
+    def max_system_atoms(self) -> int:
+        return int(np.diff(self.h_offsets).max()) if self.n_systems else 0
+
+    def struct(self) -> N.TsBatch:
+        b = N.TsBatch()
+        b.n_atoms = self.n_atoms
+        b.n_systems = self.n_systems
+        b.stride = self.pos.shape[1]
+        b.sys_offsets = self.sys_offsets.data_ptr()
+        b.h_sys_offsets = self.h_offsets.ctypes.data
+        b.system_idx = self.system_idx.data_ptr()
+        b.pos = self.pos.data_ptr()
+        b.vel = self.vel.data_ptr()
+        b.mass = None if self.mass is None else self.mass.data_ptr()
+        b.species = None if self.species is None else self.species.data_ptr()
+        b.cell = self.cell.data_ptr()
+        return b
+
+    def positions(self) -> np.ndarray:
+        return self.pos.T.cpu().numpy().copy()
+
+    def velocities(self) -> np.ndarray:
+        return self.vel.T.cpu().numpy().copy()
+
+    def cells(self) -> np.ndarray:
+        return self.cell.cpu().numpy().copy()
+
+    def clone(self) -> "Batch":
+        c = object.__new__(Batch)
+        c.__dict__.update(self.__dict__)
+        c.pos, c.vel, c.cell = self.pos.clone(), self.vel.clone(), self.cell.clone()
+        return c
+
+
+def pair_params(kind: str, params, cutoff: float, shift_energy: bool = False, prec: str = "f32") -> N.TsPairParams:
+    p = np.asarray(params, dtype=np.float64)
+    ns = p.shape[0]
+    if ns > N.TS_MAX_SPECIES:
+        raise ValueError("at most 4 species")
+    pp = N.TsPairParams()
+    pp.kind = N.KIND_CODES[kind]
+    pp.prec = N.PREC_CODES[prec]
+    pp.n_species = ns
+    pp.shift_energy = 1 if shift_energy else 0
+    pp.cutoff = float(cutoff)
+    full = np.zeros((N.TS_MAX_SPECIES, N.TS_MAX_SPECIES, 3))
+    full[:ns, :ns] = p
+    for k, v in enumerate(full.reshape(-1)):
+        pp.params[k] = float(v)
+    return pp
+
+
+def pair_params_from_spec(spec, prec: str = "f32") -> N.TsPairParams:
+    return pair_params(spec.kind, spec.params, spec.cutoff, spec.shift_energy, prec)
+
+
+# ----------------------------------------------------------------------------- neighbor list
+
+
+class NeighborList:
+    """Padded neighbor list of a batch (rows [max_nbr][N] of packed (j, S) entries)."""
+
+    def __init__(self, batch: Batch, cutoff: float, skin: float, max_nbr: int, bin_factor: int = 1, half: bool = False):
+        self.cutoff, self.skin, self.half, self.bin_factor = float(cutoff), float(skin), bool(half), int(bin_factor)
+        self.n_atoms, self.n_systems = batch.n_atoms, batch.n_systems
+        self._alloc(batch, int(max_nbr))
+
+    def _alloc(self, batch, max_nbr):
+        dev = batch.device
+        stride = batch.pos.shape[1]
+        self.max_nbr = max_nbr
+        self.nbr = torch.zeros((max_nbr, stride), dtype=torch.int32, device=dev)
+        self.n_nbr = torch.zeros(batch.n_atoms, dtype=torch.int32, device=dev)
+        self.ref_pos = torch.zeros((3, stride), dtype=torch.float64, device=dev)
+        self.ref_cell = torch.zeros((batch.n_systems, 9), dtype=torch.float64, device=dev)
+        self.status = torch.zeros(N.TS_STATUS_WORDS, dtype=torch.int64, device=dev)
+        ws = int(N.lib().ts_neighbor_workspace_bytes(batch.n_atoms, batch.n_systems))
+        self.workspace = torch.zeros(ws, dtype=torch.uint8, device=dev)
+
+    def struct(self) -> N.TsNeighborList:
+        s = N.TsNeighborList()
+        s.cutoff = self.cutoff
+        s.skin = self.skin
+        s.half = 1 if self.half else 0
+        s.max_nbr = self.max_nbr
+        s.bin_factor = self.bin_factor
+        s.nbr = self.nbr.data_ptr()
+        s.n_nbr = self.n_nbr.data_ptr()
+        s.ref_pos = self.ref_pos.data_ptr()
+        s.ref_cell = self.ref_cell.data_ptr()
+        s.status = self.status.data_ptr()
+        s.workspace = self.workspace.data_ptr()
+        s.workspace_bytes = self.workspace.numel()
+        return s
+
+    def read_status(self) -> np.ndarray:
+        return self.status.cpu().numpy()
+
+    def entries(self):
+        """Host copy of the list: (i, j_local, S0, S1, S2) arrays over all stored entries."""
+        nbr = self.nbr.cpu().numpy().astype(np.uint32)
+        n = self.n_nbr.cpu().numpy()
+        rows = []
+        for k in range(self.max_nbr):
+            sel = np.nonzero(n > k)[0]
+            if sel.size == 0:
+                break
+            e = nbr[k, sel]
+            rows.append((sel, (e & 0x1FFFF).astype(np.int64), ((e >> 17) & 31).astype(np.int64) - 16,
+                         ((e >> 22) & 31).astype(np.int64) - 16, ((e >> 27) & 31).astype(np.int64) - 16))
+        if not rows:
+            z = np.zeros(0, np.int64)
+            return z, z, z, z, z
+        return tuple(np.concatenate([r[c] for r in rows]) for c in range(5))
+
+
+def estimate_max_nbr(batch: Batch, r_list: float, margin: float = 1.3) -> int:
+    counts = np.diff(batch.h_offsets)
+    vols = np.abs(np.linalg.det(batch.cell.cpu().numpy()))
+    rho = float((counts / np.maximum(vols, 1e-300)).max())
+    return int(math.ceil(margin * 4.0 / 3.0 * math.pi * r_list ** 3 * rho)) + 16
+
+
+def build_neighbor_list(batch: Batch, cutoff: float, skin: float, bin_factor: int = 1, max_nbr: Optional[int] = None,
+                        margin: float = 1.25, half: bool = False) -> NeighborList:
+    """Allocate and build a list, regrowing once if the first capacity guess was too small."""
+    guess = max_nbr or estimate_max_nbr(batch, cutoff + skin)
+    nl = NeighborList(batch, cutoff, skin, guess, bin_factor, half)
+    ts_neighbor_build(batch, nl, force=True)
+    st = nl.read_status()
+    if st[N.TS_STATUS_NONFINITE] or st[N.TS_STATUS_SHIFT]:
+        raise RuntimeError(f"neighbor build status {st.tolist()}")
+    if st[N.TS_STATUS_OVERFLOW] or (max_nbr is None and st[N.TS_STATUS_MAX_NBR] * margin > guess):
+        need = int(math.ceil(st[N.TS_STATUS_MAX_NBR] * margin)) + 8
+        nl._alloc(batch, max(need, 1))
+        ts_neighbor_build(batch, nl, force=True)
+        st = nl.read_status()
+        if st[N.TS_STATUS_OVERFLOW]:
+            raise RuntimeError("neighbor list overflow after regrowth")
+    return nl
+
+
+# ----------------------------------------------------------------------------- FIRE state
+
+
+def fire_config(dt_start=0.1, dt_max=1.0, alpha_start=0.1, f_inc=1.1, f_dec=0.5, f_alpha=0.99, fmax=0.01,
+                cell_mass=1.0, n_min=5, relax_cell=False, max_iter=100000) -> N.TsFireConfig:
+    c = N.TsFireConfig()
+    c.dt_start, c.dt_max, c.alpha_start = dt_start, dt_max, alpha_start
+    c.f_inc, c.f_dec, c.f_alpha, c.fmax, c.cell_mass = f_inc, f_dec, f_alpha, fmax, cell_mass
+    c.n_min, c.relax_cell, c.max_iter = int(n_min), 1 if relax_cell else 0, int(max_iter)
+    return c
+
+
+class FireState:
+    def __init__(self, batch: Batch, cfg: N.TsFireConfig):
+        S, dev = batch.n_systems, batch.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.dt = torch.full((S,), cfg.dt_start, **f64)
+        self.alpha = torch.full((S,), cfg.alpha_start, **f64)
+        self.n_pos = torch.zeros(S, dtype=torch.int32, device=dev)
+        self.converged = torch.zeros(S, dtype=torch.int32, device=dev)
+        self.n_iter = torch.zeros(S, dtype=torch.int64, device=dev)
+        self.deform = torch.eye(3, **f64).reshape(1, 9).repeat(S, 1).contiguous()
+        self.deform_vel = torch.zeros((S, 9), **f64)
+        self.ref_cell = batch.cell.reshape(S, 9).clone()
+        self.scratch = torch.zeros((S, 32), **f64)
+        batch.vel.zero_()
+
+    def struct(self) -> N.TsFireState:
+        s = N.TsFireState()
+        s.dt, s.alpha, s.n_pos = self.dt.data_ptr(), self.alpha.data_ptr(), self.n_pos.data_ptr()
+        s.converged, s.n_iter = self.converged.data_ptr(), self.n_iter.data_ptr()
+        s.deform, s.deform_vel = self.deform.data_ptr(), self.deform_vel.data_ptr()
+        s.ref_cell, s.scratch = self.ref_cell.data_ptr(), self.scratch.data_ptr()
+        return s
+
+
+# ----------------------------------------------------------------------------- entry points
+
+
+def ts_neighbor_build(batch: Batch, nl: NeighborList, force: bool = True, stream=None):
+    return N.check("ts_neighbor_build", N.lib().ts_neighbor_build(ctypes.byref(batch.struct()),
+                                                                  ctypes.byref(nl.struct()), 1 if force else 0,
+                                                                  _stream(stream)))
+
+
+def ts_pair_forces(batch, nl, pp, force, energy=None, virial=None, stream=None):
+    return N.check("ts_pair_forces", N.lib().ts_pair_forces(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
+                                                            ctypes.byref(pp), _p(force), _p(energy), _p(virial),
+                                                            _stream(stream)))
+
+
+def ts_nve_step(batch, nl, pp, dt, accel, n_steps, force, epot=None, ekin=None, virial=None, use_graph=True,
+                stream=None):
+    return N.check("ts_nve_step", N.lib().ts_nve_step(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
+                                                      ctypes.byref(pp), float(dt), float(accel), int(n_steps),
+                                                      _p(force), _p(epot), _p(ekin), _p(virial),
+                                                      1 if use_graph else 0, _stream(stream)))
+
+
+def ts_fire_step(batch, fs: FireState, cfg, nl, pp, n_iter, force, energy=None, virial=None, stream=None):
+    return N.check("ts_fire_step", N.lib().ts_fire_step(ctypes.byref(batch.struct()), ctypes.byref(fs.struct()),
+                                                        ctypes.byref(cfg), ctypes.byref(nl.struct()),
+                                                        ctypes.byref(pp), int(n_iter), _p(force), _p(energy),
+                                                        _p(virial), _stream(stream)))
+
+
+def ts_pair_adjoint(batch, nl, pp, dt_drift, w_kick, accel, adj_pos, adj_vel, adj_params=None, stream=None):
+    return N.check("ts_pair_adjoint", N.lib().ts_pair_adjoint(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
+                                                              ctypes.byref(pp), float(dt_drift), float(w_kick),
+                                                              float(accel), _p(adj_pos), _p(adj_vel),
+                                                              _p(adj_params), _stream(stream)))
+
+
+def ts_rdf_smeared(batch, nl, n_bins, r_end, sigma, r_max, g, stream=None):
+    return N.check("ts_rdf_smeared", N.lib().ts_rdf_smeared(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
+                                                            int(n_bins), float(r_end), float(sigma), float(r_max),
+                                                            _p(g), _stream(stream)))
+
+
+def ts_rdf_loss(g, g_target, loss=None, dl_dg=None, stream=None):
+    S, nb = g.shape
+    return N.check("ts_rdf_loss", N.lib().ts_rdf_loss(_p(g), _p(g_target), int(S), int(nb), _p(loss), _p(dl_dg),
+                                                      _stream(stream)))
+
+
+def ts_rdf_vjp(batch, nl, n_bins, r_end, sigma, r_max, dl_dg, grad_pos, stream=None):
+    return N.check("ts_rdf_vjp", N.lib().ts_rdf_vjp(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
+                                                    int(n_bins), float(r_end), float(sigma), float(r_max), _p(dl_dg),
+                                                    _p(grad_pos), _stream(stream)))
+
+
+def ts_kinetic_energy(batch, accel, ekin, stream=None):
+    return N.check("ts_kinetic_energy", N.lib().ts_kinetic_energy(ctypes.byref(batch.struct()), float(accel),
+                                                                  _p(ekin), _stream(stream)))
+
+
+def ts_release_graphs():
+    N.lib().ts_release_graphs()
+
+
+# ----------------------------------------------------------------------------- conveniences
+
+
+def force_buffer(batch: Batch, prec: str) -> torch.Tensor:
+    dt = torch.float32 if prec == "f32" else torch.float64
+    return torch.zeros((3, batch.pos.shape[1]), dtype=dt, device=batch.device)
+
+
+def compute_forces(batch: Batch, nl: NeighborList, pp, prec: str):
+    """Forces (3, N), energies (S,), virials (S, 9) at the batch's current positions."""
+    F = force_buffer(batch, prec)
+    E = torch.zeros(batch.n_systems, dtype=torch.float64, device=batch.device)
+    W = torch.zeros((batch.n_systems, 9), dtype=torch.float64, device=batch.device)
+    ts_pair_forces(batch, nl, pp, F, E, W)
+    return F, E, W

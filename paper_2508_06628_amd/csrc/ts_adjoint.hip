@@ -1,0 +1,389 @@
+// Adjoint of the pair step and the velocity-Verlet integrator, and the Gaussian-smeared RDF
+// observable with its vector-Jacobian product (differentiable simulation, paper Section 2:
+// gradients of an RDF computed at the end of a trajectory with respect to potential parameters).
+//
+// Per pair (i, j, S), with d = r_j - r_i + S cell, r = |d|, g = phi'/r, h = phi'' and
+// du = u_j - u_i, the Hessian-vector product added to atom i is
+//     K du = (h - g) (d . du) / r^2 d + g du,
+// and the parameter term is (dg/dtheta)(u_i . d).  Pair arithmetic in the pair precision,
+// accumulators in float64.
+#include "ts_forces.h"
+
+namespace ts {
+
+struct AdjArgs {
+  int64_t n, stride;
+  const int32_t *sys_idx;
+  const int64_t *offs;
+  const double *pos, *cell, *mass;
+  const int32_t *species;
+  const uint32_t *nbr;
+  const int32_t *n_nbr;
+  double *lr;        // adj_pos (in/out)
+  const double *lv;  // adj_vel (read)
+  double *adj_params;
+  double w, accel;
+};
+
+__global__ void k_adj_drift(int64_t n, int64_t st, const double *__restrict__ lr, double *__restrict__ lv, double dt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) lv[c * st + i] = lv[c * st + i] + dt * lr[c * st + i];
+}
+
+template <int KIND, typename T, bool SINGLE>
+__global__ void __launch_bounds__(256) k_pair_vjp(AdjArgs a, PairTable tab) {
+  __shared__ double acc[TS_MAX_SPECIES * TS_MAX_SPECIES * 3];
+  if (!SINGLE) {
+    for (int k = threadIdx.x; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += blockDim.x) acc[k] = 0.0;
+    __syncthreads();
+  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < a.n;
+  double tp0 = 0.0, tp1 = 0.0, tp2 = 0.0;
+  if (valid) {
+    const int64_t st = a.stride;
+    const int s = a.sys_idx[i];
+    const int64_t a0 = a.offs[s];
+    const double *h = a.cell + 9 * (int64_t)s;
+    const double rx = a.pos[i], ry = a.pos[st + i], rz = a.pos[2 * st + i];
+    const double sci = a.mass ? a.accel / a.mass[i] : a.accel;
+    const double uix = sci * a.lv[i], uiy = sci * a.lv[st + i], uiz = sci * a.lv[2 * st + i];
+    const int si = (SINGLE || a.species == nullptr) ? 0 : a.species[i];
+    const int nn = a.n_nbr[i];
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+    const PairCoef pc0 = tab.c[0];
+    for (int k = 0; k < nn; ++k) {
+      const uint32_t ent = a.nbr[(int64_t)k * st + i];
+      const int64_t j = a0 + entry_j(ent);
+      const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
+      const double dx = (a.pos[j] - rx) + (S0 * h[0] + S1 * h[3] + S2 * h[6]);
+      const double dy = (a.pos[st + j] - ry) + (S0 * h[1] + S1 * h[4] + S2 * h[7]);
+      const double dz = (a.pos[2 * st + j] - rz) + (S0 * h[2] + S1 * h[5] + S2 * h[8]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (!(r2 < tab.cut2)) continue;
+      const int sj = (SINGLE || a.species == nullptr) ? 0 : a.species[j];
+      const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : tab.c[si * TS_MAX_SPECIES + sj];
+      if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
+      const double scj = a.mass ? a.accel / a.mass[j] : a.accel;
+      const double dux = scj * a.lv[j] - uix, duy = scj * a.lv[st + j] - uiy, duz = scj * a.lv[2 * st + j] - uiz;
+      T g, hh;
+      pair_g_h<KIND, T>(pc, (T)r2, r2, &g, &hh);
+      const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
+      const T ux = (T)dux, uy = (T)duy, uz = (T)duz;
+      const T proj = tx * ux + ty * uy + tz * uz;
+      const T coef = (hh - g) * proj / (T)r2;
+      jx += (double)(coef * tx + g * ux);
+      jy += (double)(coef * ty + g * uy);
+      jz += (double)(coef * tz + g * uz);
+      if (a.adj_params) {
+        double dg[3];
+        pair_dg_dparams<KIND>(pc, r2, dg);
+        const double ud = uix * dx + uiy * dy + uiz * dz;
+        if (SINGLE) {
+          tp0 += dg[0] * ud;
+          tp1 += dg[1] * ud;
+          tp2 += dg[2] * ud;
+        } else {
+          double *q = acc + 3 * (si * TS_MAX_SPECIES + sj);
+          atomicAdd(&q[0], a.w * dg[0] * ud);
+          atomicAdd(&q[1], a.w * dg[1] * ud);
+          atomicAdd(&q[2], a.w * dg[2] * ud);
+        }
+      }
+    }
+    a.lr[i] = a.lr[i] + a.w * jx;
+    a.lr[st + i] = a.lr[st + i] + a.w * jy;
+    a.lr[2 * st + i] = a.lr[2 * st + i] + a.w * jz;
+  }
+  if (a.adj_params) {
+    if (SINGLE) {
+      const double t0 = wave_sum(a.w * tp0), t1 = wave_sum(a.w * tp1), t2 = wave_sum(a.w * tp2);
+      if (__lane_id() == 0) {
+        atomicAdd(&a.adj_params[0], t0);
+        atomicAdd(&a.adj_params[1], t1);
+        atomicAdd(&a.adj_params[2], t2);
+      }
+    } else {
+      __syncthreads();
+      for (int k = threadIdx.x; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += blockDim.x)
+        if (acc[k] != 0.0) atomicAdd(&a.adj_params[k], acc[k]);
+    }
+  }
+}
+
+template <int KIND, typename T>
+static void launch_vjp(const AdjArgs &a, const PairTable &t, bool single, hipStream_t st) {
+  const dim3 g((unsigned)ceil_div(a.n, 256));
+  if (single)
+    hipLaunchKernelGGL((k_pair_vjp<KIND, T, true>), g, dim3(256), 0, st, a, t);
+  else
+    hipLaunchKernelGGL((k_pair_vjp<KIND, T, false>), g, dim3(256), 0, st, a, t);
+}
+
+// ----------------------------------------------------------------------------- RDF
+
+__device__ inline double cell_volume(const double *h) {
+  return fabs(h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
+              h[2] * (h[3] * h[7] - h[4] * h[6]));
+}
+
+struct RdfArgs {
+  int64_t n, stride;
+  const int32_t *sys_idx;
+  const int64_t *offs;
+  const double *pos, *cell;
+  const uint32_t *nbr;
+  const int32_t *n_nbr;
+  int n_bins;
+  double dr, sigma, rmax2;
+};
+
+// Histogram of exp(-(r_b - r)^2 / 2 sigma^2) over ordered pairs (bins within 10 sigma of r).
+__global__ void __launch_bounds__(256) k_rdf_hist(RdfArgs a, double *g) {
+  extern __shared__ double lh[];
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+  const int s_blk = a.sys_idx[first < a.n ? first : a.n - 1];
+  for (int b = threadIdx.x; b < a.n_bins; b += blockDim.x) lh[b] = 0.0;
+  __syncthreads();
+  const int64_t i = first + threadIdx.x;
+  if (i < a.n) {
+    const int64_t st = a.stride;
+    const int s = a.sys_idx[i];
+    const int64_t a0 = a.offs[s];
+    const double *h = a.cell + 9 * (int64_t)s;
+    const double rx = a.pos[i], ry = a.pos[st + i], rz = a.pos[2 * st + i];
+    const int nn = a.n_nbr[i];
+    const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
+    const double span = 10.0 * a.sigma;
+    for (int k = 0; k < nn; ++k) {
+      const uint32_t ent = a.nbr[(int64_t)k * st + i];
+      const int64_t j = a0 + entry_j(ent);
+      const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
+      const double dx = (a.pos[j] - rx) + (S0 * h[0] + S1 * h[3] + S2 * h[6]);
+      const double dy = (a.pos[st + j] - ry) + (S0 * h[1] + S1 * h[4] + S2 * h[7]);
+      const double dz = (a.pos[2 * st + j] - rz) + (S0 * h[2] + S1 * h[5] + S2 * h[8]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (!(r2 < a.rmax2)) continue;
+      const double r = sqrt(r2);
+      int b0 = (int)floor((r - span) / a.dr - 0.5);
+      int b1 = (int)ceil((r + span) / a.dr - 0.5);
+      b0 = b0 < 0 ? 0 : b0;
+      b1 = b1 > a.n_bins - 1 ? a.n_bins - 1 : b1;
+      for (int b = b0; b <= b1; ++b) {
+        const double x = (b + 0.5) * a.dr - r;
+        const double v = exp(-x * x * inv2s2);
+        if (s == s_blk)
+          atomicAdd(&lh[b], v);
+        else
+          atomicAdd(&g[(int64_t)s * a.n_bins + b], v);
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < a.n_bins; b += blockDim.x)
+    if (lh[b] != 0.0) atomicAdd(&g[(int64_t)s_blk * a.n_bins + b], lh[b]);
+}
+
+// g[s][b] *= 1 / (sqrt(2 pi) sigma 4 pi r_b^2 rho_s N_s)
+__global__ void k_rdf_norm(int64_t n_sys, const int64_t *offs, const double *cell, int n_bins, double dr, double sigma,
+                           double *g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_sys * n_bins) return;
+  const int64_t s = t / n_bins;
+  const int b = (int)(t % n_bins);
+  const double na = (double)(offs[s + 1] - offs[s]);
+  const double rho = na / cell_volume(cell + 9 * s);
+  const double rb = (b + 0.5) * dr;
+  const double norm = 1.0 / sqrt(2.0 * M_PI * sigma * sigma);
+  g[t] = g[t] * norm / (4.0 * M_PI * rb * rb * rho * na);
+}
+
+__global__ void __launch_bounds__(256) k_rdf_loss(const double *g, const double *gt, int64_t m, double inv_m,
+                                                  double *loss, double *dl) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+    const double e = g[t] - gt[t];
+    acc += e * e;
+    if (dl) dl[t] = 2.0 * e * inv_m;
+  }
+  acc = wave_sum(acc);
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) *loss = ((sh[0] + sh[1]) + (sh[2] + sh[3])) * inv_m;
+}
+
+// grad_i += -2 sum_{(j,S)} [sum_b pref_b dN(r_b - r)/dr] d^
+__global__ void __launch_bounds__(256) k_rdf_vjp(RdfArgs a, const double *dl_dg, double *grad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t st = a.stride;
+  const int s = a.sys_idx[i];
+  const int64_t a0 = a.offs[s];
+  const double *h = a.cell + 9 * (int64_t)s;
+  const double na = (double)(a.offs[s + 1] - a0);
+  const double rho = na / cell_volume(h);
+  const double norm = 1.0 / sqrt(2.0 * M_PI * a.sigma * a.sigma);
+  const double *dg = dl_dg + (int64_t)s * a.n_bins;
+  const double rx = a.pos[i], ry = a.pos[st + i], rz = a.pos[2 * st + i];
+  const int nn = a.n_nbr[i];
+  const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
+  const double invs2 = 1.0 / (a.sigma * a.sigma);
+  const double span = 10.0 * a.sigma;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int k = 0; k < nn; ++k) {
+    const uint32_t ent = a.nbr[(int64_t)k * st + i];
+    const int64_t j = a0 + entry_j(ent);
+    const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
+    const double dx = (a.pos[j] - rx) + (S0 * h[0] + S1 * h[3] + S2 * h[6]);
+    const double dy = (a.pos[st + j] - ry) + (S0 * h[1] + S1 * h[4] + S2 * h[7]);
+    const double dz = (a.pos[2 * st + j] - rz) + (S0 * h[2] + S1 * h[5] + S2 * h[8]);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < a.rmax2)) continue;
+    const double r = sqrt(r2);
+    int b0 = (int)floor((r - span) / a.dr - 0.5);
+    int b1 = (int)ceil((r + span) / a.dr - 0.5);
+    b0 = b0 < 0 ? 0 : b0;
+    b1 = b1 > a.n_bins - 1 ? a.n_bins - 1 : b1;
+    double hs = 0.0;
+    for (int b = b0; b <= b1; ++b) {
+      const double rb = (b + 0.5) * a.dr;
+      const double x = rb - r;
+      const double pref = dg[b] * norm / (4.0 * M_PI * rb * rb * rho * na);
+      hs += pref * exp(-x * x * inv2s2) * x * invs2;
+    }
+    const double c = -2.0 * hs / r;
+    gx += c * dx;
+    gy += c * dy;
+    gz += c * dz;
+  }
+  grad[i] += gx;
+  grad[st + i] += gy;
+  grad[2 * st + i] += gz;
+}
+
+static RdfArgs make_rdf_args(const ts_batch *b, const ts_neighbor_list *nl, int n_bins, double r_end, double sigma,
+                             double r_max) {
+  RdfArgs a;
+  a.n = b->n_atoms;
+  a.stride = stride_of(b);
+  a.sys_idx = b->system_idx;
+  a.offs = b->sys_offsets;
+  a.pos = b->pos;
+  a.cell = b->cell;
+  a.nbr = reinterpret_cast<const uint32_t *>(nl->nbr);
+  a.n_nbr = nl->n_nbr;
+  a.n_bins = n_bins;
+  a.dr = r_end / n_bins;
+  a.sigma = sigma;
+  a.rmax2 = r_max * r_max;
+  return a;
+}
+
+static int validate_rdf(const ts_batch *b, const ts_neighbor_list *nl, int n_bins, double r_end, double sigma,
+                        double r_max) {
+  int rc = validate_batch(b, false, nullptr);
+  if (rc != TS_OK) return rc;
+  rc = validate_list(b, nl);
+  if (rc != TS_OK) return rc;
+  if (nl->half) return TS_E_UNSUPPORTED;
+  TS_CHECK_ARG(n_bins >= 1 && n_bins <= 8192 && r_end > 0.0 && sigma > 0.0 && r_max > 0.0);
+  TS_CHECK_ARG(nl->cutoff + nl->skin >= r_max);
+  return TS_OK;
+}
+
+}  // namespace ts
+
+extern "C" int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp,
+                               double dt_drift, double w_kick, double accel, double *adj_pos, double *adj_vel,
+                               double *adj_params, ts_stream_t stream) {
+  int64_t max_atoms = 0;
+  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, false);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(adj_pos && adj_vel && std::isfinite(dt_drift) && std::isfinite(w_kick) && std::isfinite(accel) &&
+               accel > 0.0);
+  hipStream_t st = ts::as_stream(stream);
+  if (batch->n_atoms == 0) return TS_OK;
+  const int64_t stride = ts::stride_of(batch);
+  if (dt_drift != 0.0) {
+    hipLaunchKernelGGL(ts::k_adj_drift, dim3((unsigned)ts::ceil_div(batch->n_atoms, 256)), dim3(256), 0, st,
+                       batch->n_atoms, stride, adj_pos, adj_vel, dt_drift);
+    TS_LAUNCH_CHECK();
+  }
+  if (w_kick == 0.0) return TS_OK;
+  ts::AdjArgs a;
+  a.n = batch->n_atoms;
+  a.stride = stride;
+  a.sys_idx = batch->system_idx;
+  a.offs = batch->sys_offsets;
+  a.pos = batch->pos;
+  a.cell = batch->cell;
+  a.mass = batch->mass;
+  a.species = batch->species;
+  a.nbr = reinterpret_cast<const uint32_t *>(nl->nbr);
+  a.n_nbr = nl->n_nbr;
+  a.lr = adj_pos;
+  a.lv = adj_vel;
+  a.adj_params = adj_params;
+  a.w = w_kick;
+  a.accel = accel;
+  const ts::PairTable t = ts::make_table(pp);
+  const bool single = t.n_species == 1 || batch->species == nullptr;
+  if (pp->prec == TS_PAIR_F32) {
+    if (t.kind == TS_LJ) ts::launch_vjp<TS_LJ, float>(a, t, single, st);
+    else if (t.kind == TS_MORSE) ts::launch_vjp<TS_MORSE, float>(a, t, single, st);
+    else ts::launch_vjp<TS_SOFT_SPHERE, float>(a, t, single, st);
+  } else {
+    if (t.kind == TS_LJ) ts::launch_vjp<TS_LJ, double>(a, t, single, st);
+    else if (t.kind == TS_MORSE) ts::launch_vjp<TS_MORSE, double>(a, t, single, st);
+    else ts::launch_vjp<TS_SOFT_SPHERE, double>(a, t, single, st);
+  }
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+extern "C" int ts_rdf_smeared(const ts_batch *batch, const ts_neighbor_list *nl, int32_t n_bins, double r_end,
+                              double sigma, double r_max, double *g, ts_stream_t stream) {
+  int rc = ts::validate_rdf(batch, nl, n_bins, r_end, sigma, r_max);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(g != nullptr);
+  hipStream_t st = ts::as_stream(stream);
+  const int64_t m = batch->n_systems * (int64_t)n_bins;
+  rc = ts::fill_async<double>(g, m, 0.0, st);
+  if (rc != TS_OK) return rc;
+  const ts::RdfArgs a = ts::make_rdf_args(batch, nl, n_bins, r_end, sigma, r_max);
+  if (batch->n_atoms > 0) {
+    hipLaunchKernelGGL(ts::k_rdf_hist, dim3((unsigned)ts::ceil_div(batch->n_atoms, 256)), dim3(256),
+                       sizeof(double) * n_bins, st, a, g);
+    TS_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(ts::k_rdf_norm, dim3((unsigned)ts::ceil_div(m, 256)), dim3(256), 0, st, batch->n_systems,
+                     batch->sys_offsets, batch->cell, n_bins, r_end / n_bins, sigma, g);
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+extern "C" int ts_rdf_loss(const double *g, const double *g_target, int64_t n_systems, int32_t n_bins, double *loss,
+                           double *dl_dg, ts_stream_t stream) {
+  TS_CHECK_ARG(g && g_target && n_systems >= 1 && n_bins >= 1);
+  const int64_t m = n_systems * (int64_t)n_bins;
+  hipLaunchKernelGGL(ts::k_rdf_loss, dim3(1), dim3(256), 0, ts::as_stream(stream), g, g_target, m, 1.0 / (double)m,
+                     loss, dl_dg);
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+extern "C" int ts_rdf_vjp(const ts_batch *batch, const ts_neighbor_list *nl, int32_t n_bins, double r_end,
+                          double sigma, double r_max, const double *dl_dg, double *grad_pos, ts_stream_t stream) {
+  int rc = ts::validate_rdf(batch, nl, n_bins, r_end, sigma, r_max);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(dl_dg && grad_pos);
+  if (batch->n_atoms == 0) return TS_OK;
+  const ts::RdfArgs a = ts::make_rdf_args(batch, nl, n_bins, r_end, sigma, r_max);
+  hipLaunchKernelGGL(ts::k_rdf_vjp, dim3((unsigned)ts::ceil_div(batch->n_atoms, 256)), dim3(256), 0,
+                     ts::as_stream(stream), a, dl_dg, grad_pos);
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}

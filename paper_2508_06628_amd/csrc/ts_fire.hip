@@ -1,0 +1,276 @@
+// FIRE relaxation of positions, or positions and cell, for every system of a batch (the
+// structural relaxation optimizers of the paper's Abstract; relaxation is the variable-length
+// workload of Section 3).  Each iteration is: neighbor validity test/rebuild, pair forces of the
+// unconverged systems, and one workgroup per system that reduces the FIRE scalars of its system
+// (max |F|, g.v, |v|^2, |g|^2 in a fixed order), takes the FIRE decision and updates the
+// system's atoms (and cell) -- no grid-wide synchronisation inside an iteration's update.
+#include "ts_forces.h"
+#include "ts_neighbor.h"
+
+namespace ts {
+
+struct FireArgs {
+  int64_t stride;
+  const int64_t *offs;
+  double *pos, *vel;
+  const double *mass;
+  double *cell;
+  const void *force;
+  const double *virial;  // [S][9] (relax_cell)
+  double *dt, *alpha;
+  int32_t *n_pos, *converged;
+  int64_t *n_iter;
+  double *deform, *deform_vel, *ref_cell;
+  ts_fire_config cfg;
+};
+
+__device__ inline void inv3d(const double *h, double *inv) {
+  const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
+                     h[2] * (h[3] * h[7] - h[4] * h[6]);
+  const double id = 1.0 / det;
+  inv[0] = (h[4] * h[8] - h[5] * h[7]) * id;
+  inv[1] = (h[2] * h[7] - h[1] * h[8]) * id;
+  inv[2] = (h[1] * h[5] - h[2] * h[4]) * id;
+  inv[3] = (h[5] * h[6] - h[3] * h[8]) * id;
+  inv[4] = (h[0] * h[8] - h[2] * h[6]) * id;
+  inv[5] = (h[2] * h[3] - h[0] * h[5]) * id;
+  inv[6] = (h[3] * h[7] - h[4] * h[6]) * id;
+  inv[7] = (h[1] * h[6] - h[0] * h[7]) * id;
+  inv[8] = (h[0] * h[4] - h[1] * h[3]) * id;
+}
+
+// Block (256 threads) reductions with a fixed combination order.
+__device__ inline double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+__device__ inline double block_max(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// One workgroup per system.  final_check = 1: only the convergence test (no update).
+template <typename T, bool CELL>
+__global__ void __launch_bounds__(256) k_fire_update(FireArgs a, int final_check) {
+  const int s = blockIdx.x;
+  if (a.converged[s]) return;
+  const int64_t a0 = a.offs[s], a1 = a.offs[s + 1];
+  const int64_t na = a1 - a0;
+  const int64_t st = a.stride;
+  const T *F = static_cast<const T *>(a.force);
+  __shared__ double sh[4];
+  __shared__ double co[24];  // 0 cv, 1 cg, 2 dt, 3 skip, 4..12 D^-1, 13..21 D_new
+  double D[9];
+  if (CELL) {
+    for (int k = 0; k < 9; ++k) D[k] = a.deform[9 * s + k];
+  }
+  double fmax2 = 0.0, P = 0.0, vv = 0.0, gg = 0.0;
+  for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+    const double f0 = (double)F[i], f1 = (double)F[st + i], f2 = (double)F[2 * st + i];
+    fmax2 = fmax(fmax2, f0 * f0 + f1 * f1 + f2 * f2);
+    double g0 = f0, g1 = f1, g2 = f2;
+    if (CELL) {
+      g0 = f0 * D[0] + f1 * D[1] + f2 * D[2];
+      g1 = f0 * D[3] + f1 * D[4] + f2 * D[5];
+      g2 = f0 * D[6] + f1 * D[7] + f2 * D[8];
+    }
+    const double v0 = a.vel[i], v1 = a.vel[st + i], v2 = a.vel[2 * st + i];
+    P += g0 * v0 + g1 * v1 + g2 * v2;
+    vv += v0 * v0 + v1 * v1 + v2 * v2;
+    gg += g0 * g0 + g1 * g1 + g2 * g2;
+  }
+  fmax2 = block_max(fmax2, sh);
+  P = block_sum(P, sh);
+  vv = block_sum(vv, sh);
+  gg = block_sum(gg, sh);
+  if (threadIdx.x == 0) {
+    const ts_fire_config &c = a.cfg;
+    bool conv = sqrt(fmax2) < c.fmax;
+    double Di[9], G[9], V[9];
+    if (CELL) {
+      inv3d(D, Di);
+      const double *W = a.virial + 9 * s;
+      double gmax = 0.0;
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+          // G = D^-T W / N
+          const double v = (Di[0 * 3 + p] * W[0 * 3 + q] + Di[1 * 3 + p] * W[1 * 3 + q] + Di[2 * 3 + p] * W[2 * 3 + q]) /
+                           (double)na;
+          G[3 * p + q] = v;
+          gmax = fmax(gmax, fabs(v));
+        }
+      conv = conv && gmax < c.fmax;
+      for (int k = 0; k < 9; ++k) V[k] = a.deform_vel[9 * s + k];
+    }
+    double skip = 0.0;
+    if (conv) {
+      a.converged[s] = 1;
+      skip = 1.0;
+    } else if (final_check || a.n_iter[s] >= c.max_iter) {
+      skip = 1.0;
+    } else {
+      double dt = a.dt[s], al = a.alpha[s];
+      int np = a.n_pos[s];
+      double cv = 1.0, cg = 0.0;
+      if (a.n_iter[s] > 0) {
+        double Pt = P, vvt = vv, ggt = gg;
+        if (CELL)
+          for (int k = 0; k < 9; ++k) {
+            Pt += G[k] * V[k];
+            vvt += V[k] * V[k];
+            ggt += G[k] * G[k];
+          }
+        if (Pt > 0.0) {
+          if (ggt > 0.0) {
+            cv = 1.0 - al;
+            cg = al * sqrt(vvt) / sqrt(ggt);
+          }
+          np += 1;
+          if (np > c.n_min) {
+            dt = fmin(dt * c.f_inc, c.dt_max);
+            al = al * c.f_alpha;
+          }
+        } else {
+          cv = 0.0;
+          cg = 0.0;
+          dt = dt * c.f_dec;
+          al = c.alpha_start;
+          np = 0;
+        }
+      }
+      a.dt[s] = dt;
+      a.alpha[s] = al;
+      a.n_pos[s] = np;
+      a.n_iter[s] += 1;
+      co[0] = cv;
+      co[1] = cg;
+      co[2] = dt;
+      if (CELL) {
+        double Dn[9];
+        for (int k = 0; k < 9; ++k) {
+          V[k] = cv * V[k] + cg * G[k];
+          V[k] = V[k] + dt * G[k] / c.cell_mass;
+          Dn[k] = D[k] + (dt / (double)na) * V[k];
+          a.deform_vel[9 * s + k] = V[k];
+          a.deform[9 * s + k] = Dn[k];
+          co[13 + k] = Dn[k];
+        }
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q)
+            a.cell[9 * s + 3 * p + q] = a.ref_cell[9 * s + 3 * p + 0] * Dn[0 * 3 + q] +
+                                        a.ref_cell[9 * s + 3 * p + 1] * Dn[1 * 3 + q] +
+                                        a.ref_cell[9 * s + 3 * p + 2] * Dn[2 * 3 + q];
+        // keep D^-1 for the position update (q = r D^-1 + dt v, r' = q D_new)
+        for (int k = 0; k < 9; ++k) co[4 + k] = Di[k];
+      }
+    }
+    co[3] = skip;
+  }
+  __syncthreads();
+  if (co[3] != 0.0) return;
+  const double cv = co[0], cg = co[1], dt = co[2];
+  double Di[9], Dn[9];
+  if (CELL) {
+    for (int k = 0; k < 9; ++k) {
+      Di[k] = co[4 + k];
+      Dn[k] = co[13 + k];
+    }
+  }
+  for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+    const double f0 = (double)F[i], f1 = (double)F[st + i], f2 = (double)F[2 * st + i];
+    double g[3] = {f0, f1, f2};
+    if (CELL) {
+      g[0] = f0 * D[0] + f1 * D[1] + f2 * D[2];
+      g[1] = f0 * D[3] + f1 * D[4] + f2 * D[5];
+      g[2] = f0 * D[6] + f1 * D[7] + f2 * D[8];
+    }
+    const double m = a.mass ? a.mass[i] : 1.0;
+    double v[3], r[3];
+    for (int k = 0; k < 3; ++k) {
+      v[k] = cv * a.vel[k * st + i] + cg * g[k];
+      v[k] = v[k] + dt * g[k] / m;
+      a.vel[k * st + i] = v[k];
+      r[k] = a.pos[k * st + i];
+    }
+    if (CELL) {
+      double q[3];
+      for (int k = 0; k < 3; ++k) q[k] = (r[0] * Di[k] + r[1] * Di[3 + k] + r[2] * Di[6 + k]) + dt * v[k];
+      for (int k = 0; k < 3; ++k) a.pos[k * st + i] = q[0] * Dn[k] + q[1] * Dn[3 + k] + q[2] * Dn[6 + k];
+    } else {
+      for (int k = 0; k < 3; ++k) a.pos[k * st + i] = r[k] + dt * v[k];
+    }
+  }
+}
+
+template <typename T>
+static void launch_fire_update(const FireArgs &fa, bool cell, int final_check, int64_t n_sys, hipStream_t st) {
+  if (cell)
+    hipLaunchKernelGGL((k_fire_update<T, true>), dim3((unsigned)n_sys), dim3(256), 0, st, fa, final_check);
+  else
+    hipLaunchKernelGGL((k_fire_update<T, false>), dim3((unsigned)n_sys), dim3(256), 0, st, fa, final_check);
+}
+
+}  // namespace ts
+
+extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,
+                            const ts_pair_params *pp, int64_t n_iter, void *force, double *energy, double *virial,
+                            ts_stream_t stream) {
+  int64_t max_atoms = 0;
+  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, true);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(fs && cfg && force && n_iter >= 1);
+  TS_CHECK_ARG(fs->dt && fs->alpha && fs->n_pos && fs->converged && fs->n_iter && fs->scratch);
+  TS_CHECK_ARG(cfg->fmax > 0.0 && cfg->dt_start > 0.0 && cfg->dt_max > 0.0 && cfg->f_dec > 0.0 && cfg->f_inc > 0.0);
+  const bool cell = cfg->relax_cell != 0;
+  if (cell) {
+    TS_CHECK_ARG(fs->deform && fs->deform_vel && fs->ref_cell && cfg->cell_mass > 0.0);
+    for (int64_t s = 0; s < batch->n_systems; ++s)
+      TS_CHECK_ARG(batch->h_sys_offsets[s + 1] > batch->h_sys_offsets[s]);
+  }
+  hipStream_t st = ts::as_stream(stream);
+  const ts::PairTable tab = ts::make_table(pp);
+  double *vir = virial ? virial : fs->scratch;  // scratch holds [S][9] when the caller wants no virial
+  ts::FireArgs fa;
+  fa.stride = ts::stride_of(batch);
+  fa.offs = batch->sys_offsets;
+  fa.pos = batch->pos;
+  fa.vel = batch->vel;
+  fa.mass = batch->mass;
+  fa.cell = batch->cell;
+  fa.force = force;
+  fa.virial = vir;
+  fa.dt = fs->dt;
+  fa.alpha = fs->alpha;
+  fa.n_pos = fs->n_pos;
+  fa.converged = fs->converged;
+  fa.n_iter = fs->n_iter;
+  fa.deform = fs->deform;
+  fa.deform_vel = fs->deform_vel;
+  fa.ref_cell = fs->ref_cell;
+  fa.cfg = *cfg;
+  for (int64_t it = 0; it <= n_iter; ++it) {
+    const bool last = it == n_iter;
+    rc = ts::nl_update(batch, nl, 0, max_atoms, st);
+    if (rc != TS_OK) return rc;
+    double *e = last ? energy : nullptr;
+    const bool ev = cell || (last && (energy || virial));
+    rc = ts::launch_forces(ts::make_force_args(batch, nl, force, e, ev ? vir : nullptr, fs->converged),
+                           batch->n_systems, tab, pp->prec, ev, st);
+    if (rc != TS_OK) return rc;
+    if (pp->prec == TS_PAIR_F32)
+      ts::launch_fire_update<float>(fa, cell, last ? 1 : 0, batch->n_systems, st);
+    else
+      ts::launch_fire_update<double>(fa, cell, last ? 1 : 0, batch->n_systems, st);
+    TS_LAUNCH_CHECK();
+  }
+  return TS_OK;
+}

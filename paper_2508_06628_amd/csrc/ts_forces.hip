@@ -1,0 +1,171 @@
+// Pair energy / force / virial over a padded full neighbor list (Lennard-Jones, Morse,
+// soft-sphere: the classical potentials of the paper's Abstract; output schema of energies,
+// forces and stress, Section 2).
+//
+// One lane per atom.  The pair vector d = r_j - r_i + S cell and the interaction mask are float64;
+// the pair function runs in the pair precision T; forces, energies and virials accumulate in
+// float64.  Per-system energy and virial are reduced across the wavefront and added with one
+// float64 atomic per wavefront (lanes of a wavefront almost always share a system).
+#include "ts_forces.h"
+
+namespace ts {
+
+template <int KIND, typename T, bool EV, bool SINGLE>
+__global__ void __launch_bounds__(256) k_pair_forces(ForceArgs a, PairTable tab) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = i < a.n;
+  const int64_t ii = valid ? i : 0;
+  const int s = valid ? a.sys_idx[ii] : 0;
+  if (valid && a.skip && a.skip[s]) valid = false;
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;  // xx yy zz xy xz yz
+  if (valid) {
+    const int64_t st = a.stride;
+    const int64_t a0 = a.offs[s];
+    const double *h = a.cell + 9 * (int64_t)s;
+    const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
+                 h22 = h[8];
+    const double rx = a.pos[ii], ry = a.pos[st + ii], rz = a.pos[2 * st + ii];
+    const int si = (SINGLE || a.species == nullptr) ? 0 : a.species[ii];
+    const int nn = a.n_nbr[ii];
+    const double cut2 = tab.cut2;
+    PairCoef pc0 = tab.c[0];
+    for (int k = 0; k < nn; ++k) {
+      const uint32_t ent = a.nbr[(int64_t)k * st + ii];
+      const int64_t j = a0 + entry_j(ent);
+      const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
+      const double dx = (a.pos[j] - rx) + (S0 * h00 + S1 * h10 + S2 * h20);
+      const double dy = (a.pos[st + j] - ry) + (S0 * h01 + S1 * h11 + S2 * h21);
+      const double dz = (a.pos[2 * st + j] - rz) + (S0 * h02 + S1 * h12 + S2 * h22);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (!(r2 < cut2)) continue;
+      const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : tab.c[si * TS_MAX_SPECIES + a.species[j]];
+      if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
+      const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
+      T phi = (T)0;
+      const T g = pair_g<KIND, T>(pc, (T)r2, r2, &phi, EV);
+      const T gx = g * tx, gy = g * ty, gz = g * tz;
+      fx += (double)gx;
+      fy += (double)gy;
+      fz += (double)gz;
+      if (EV) {
+        e += (double)phi;
+        w0 += (double)(gx * tx);
+        w1 += (double)(gy * ty);
+        w2 += (double)(gz * tz);
+        w3 += (double)(gx * ty);
+        w4 += (double)(gx * tz);
+        w5 += (double)(gy * tz);
+      }
+    }
+    T *F = static_cast<T *>(a.force);
+    F[ii] = (T)fx;
+    F[st + ii] = (T)fy;
+    F[2 * st + ii] = (T)fz;
+  }
+  if (EV) {
+    if (a.energy) {
+      const double ev[1] = {0.5 * e};
+      add_by_system<1>(a.energy, 1, s, valid, ev);
+    }
+    if (a.virial) {
+      const double wv[9] = {-0.5 * w0, -0.5 * w3, -0.5 * w4, -0.5 * w3, -0.5 * w1,
+                            -0.5 * w5, -0.5 * w4, -0.5 * w5, -0.5 * w2};
+      add_by_system<9>(a.virial, 9, s, valid, wv);
+    }
+  }
+}
+
+__global__ void k_zero_ev(int64_t n_sys, double *energy, double *virial, const int32_t *skip) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  if (skip && skip[s]) return;
+  if (energy) energy[s] = 0.0;
+  if (virial)
+    for (int k = 0; k < 9; ++k) virial[9 * s + k] = 0.0;
+}
+
+template <int KIND, typename T>
+static void launch_kt(const ForceArgs &a, const PairTable &t, bool ev, bool single, dim3 g, hipStream_t st) {
+  if (ev) {
+    if (single)
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, true, true>), g, dim3(256), 0, st, a, t);
+    else
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, true, false>), g, dim3(256), 0, st, a, t);
+  } else {
+    if (single)
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, false, true>), g, dim3(256), 0, st, a, t);
+    else
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, false, false>), g, dim3(256), 0, st, a, t);
+  }
+}
+
+int launch_forces(const ForceArgs &a, int64_t n_sys, const PairTable &t, int prec, bool ev, hipStream_t st) {
+  if (ev && (a.energy || a.virial)) {
+    hipLaunchKernelGGL(k_zero_ev, dim3((unsigned)ceil_div(n_sys, 64)), dim3(64), 0, st, n_sys, a.energy, a.virial,
+                       a.skip);
+    TS_LAUNCH_CHECK();
+  }
+  if (a.n == 0) return TS_OK;
+  const dim3 g((unsigned)ceil_div(a.n, 256));
+  const bool single = t.n_species == 1 || a.species == nullptr;
+  const bool do_ev = ev && (a.energy || a.virial);
+  if (prec == TS_PAIR_F32) {
+    if (t.kind == TS_LJ) launch_kt<TS_LJ, float>(a, t, do_ev, single, g, st);
+    else if (t.kind == TS_MORSE) launch_kt<TS_MORSE, float>(a, t, do_ev, single, g, st);
+    else launch_kt<TS_SOFT_SPHERE, float>(a, t, do_ev, single, g, st);
+  } else {
+    if (t.kind == TS_LJ) launch_kt<TS_LJ, double>(a, t, do_ev, single, g, st);
+    else if (t.kind == TS_MORSE) launch_kt<TS_MORSE, double>(a, t, do_ev, single, g, st);
+    else launch_kt<TS_SOFT_SPHERE, double>(a, t, do_ev, single, g, st);
+  }
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+ForceArgs make_force_args(const ts_batch *b, const ts_neighbor_list *nl, void *force, double *energy, double *virial,
+                          const int32_t *skip) {
+  ForceArgs a;
+  a.n = b->n_atoms;
+  a.stride = stride_of(b);
+  a.sys_idx = b->system_idx;
+  a.offs = b->sys_offsets;
+  a.pos = b->pos;
+  a.cell = b->cell;
+  a.species = b->species;
+  a.nbr = reinterpret_cast<const uint32_t *>(nl->nbr);
+  a.n_nbr = nl->n_nbr;
+  a.force = force;
+  a.energy = energy;
+  a.virial = virial;
+  a.skip = skip;
+  return a;
+}
+
+int validate_pair_call(const ts_batch *b, const ts_neighbor_list *nl, const ts_pair_params *pp, int64_t *max_atoms,
+                       bool need_vel) {
+  int rc = validate_batch(b, need_vel, max_atoms);
+  if (rc != TS_OK) return rc;
+  rc = validate_params(pp);
+  if (rc != TS_OK) return rc;
+  rc = validate_list(b, nl);
+  if (rc != TS_OK) return rc;
+  if (nl->half) return TS_E_UNSUPPORTED;
+  // the list must cover the interaction range
+  TS_CHECK_ARG(nl->cutoff + nl->skin >= pp->cutoff);
+  return TS_OK;
+}
+
+}  // namespace ts
+
+extern "C" int ts_pair_forces(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp, void *force,
+                              double *energy, double *virial, ts_stream_t stream) {
+  int64_t max_atoms = 0;
+  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, false);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(force != nullptr);
+  const ts::PairTable t = ts::make_table(pp);
+  const ts::ForceArgs a = ts::make_force_args(batch, nl, force, energy, virial, nullptr);
+  return ts::launch_forces(a, batch->n_systems, t, pp->prec, energy != nullptr || virial != nullptr,
+                           ts::as_stream(stream));
+}

@@ -1,0 +1,263 @@
+// Internal helpers shared by the HIP translation units of the library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "ts_api.h"
+
+namespace ts {
+
+constexpr int kWave = 64;
+
+// ----------------------------------------------------------------------------- host helpers
+
+#define TS_CHECK_ARG(cond)      \
+  do {                          \
+    if (!(cond)) return TS_E_INVALID; \
+  } while (0)
+
+#define TS_HIP(expr)                           \
+  do {                                         \
+    hipError_t _e = (expr);                    \
+    if (_e != hipSuccess) return TS_E_HIP;     \
+  } while (0)
+
+#define TS_LAUNCH_CHECK()                        \
+  do {                                           \
+    if (hipPeekAtLastError() != hipSuccess) {    \
+      (void)hipGetLastError();                   \
+      return TS_E_HIP;                           \
+    }                                            \
+  } while (0)
+
+inline int64_t stride_of(const ts_batch *b) { return b->stride > 0 ? b->stride : b->n_atoms; }
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline hipStream_t as_stream(ts_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Host-side validation of a batch; fills max_atoms (largest system).
+int validate_batch(const ts_batch *b, bool need_vel, int64_t *max_atoms);
+int validate_params(const ts_pair_params *pp);
+int validate_list(const ts_batch *b, const ts_neighbor_list *nl);
+
+// ----------------------------------------------------------------------------- list entries
+
+__host__ __device__ inline uint32_t pack_entry(int j_local, int s0, int s1, int s2) {
+  return (uint32_t)j_local | ((uint32_t)(s0 + 16) << 17) | ((uint32_t)(s1 + 16) << 22) |
+         ((uint32_t)(s2 + 16) << 27);
+}
+__device__ inline int entry_j(uint32_t e) { return (int)(e & 0x1FFFFu); }
+__device__ inline int entry_s0(uint32_t e) { return (int)((e >> 17) & 31u) - 16; }
+__device__ inline int entry_s1(uint32_t e) { return (int)((e >> 22) & 31u) - 16; }
+__device__ inline int entry_s2(uint32_t e) { return (int)((e >> 27) & 31u) - 16; }
+
+// ----------------------------------------------------------------------------- pair tables
+
+// Per species-pair coefficients prepared on the host (both precisions), passed by value.
+//   LJ:    a = 4 eps sigma^12, b = 4 eps sigma^6          phi = a/r^12 - b/r^6
+//   Morse: a = D, b = alpha, c = r0
+//   SS:    a = eps, b = sigma_ij, c = 1/sigma_ij
+//   shift: phi(r_c) when the energy is shifted, else 0.
+struct PairCoef {
+  double a, b, c, shift;
+  double sig2;  // sigma_ij^2 (soft sphere mask), else +inf
+  double raw[3];  // the caller's parameter triple (for parameter derivatives)
+};
+struct PairTable {
+  PairCoef c[TS_MAX_SPECIES * TS_MAX_SPECIES];
+  double cut2;
+  int n_species;
+  int kind;
+};
+
+PairTable make_table(const ts_pair_params *pp);
+
+// Pair function: returns g = phi'(r)/r and (optionally) phi(r) - shift.  d is the pair vector in
+// the pair precision, r2 its squared norm (float64) for masks and the soft-sphere overlap.
+template <int KIND, typename T>
+__device__ inline T pair_g(const PairCoef &pc, T r2t, double r2, T *phi, bool want_phi);
+
+template <>
+__device__ inline float pair_g<TS_LJ, float>(const PairCoef &pc, float r2t, double, float *phi, bool want_phi) {
+  const float ir2 = 1.0f / r2t;
+  const float ir6 = ir2 * ir2 * ir2;
+  const float a = (float)pc.a, b = (float)pc.b;
+  if (want_phi) *phi = ir6 * (a * ir6 - b) - (float)pc.shift;
+  return ir2 * ir6 * (6.0f * b - 12.0f * a * ir6);
+}
+template <>
+__device__ inline double pair_g<TS_LJ, double>(const PairCoef &pc, double r2t, double, double *phi, bool want_phi) {
+  const double ir2 = 1.0 / r2t;
+  const double ir6 = ir2 * ir2 * ir2;
+  if (want_phi) *phi = ir6 * (pc.a * ir6 - pc.b) - pc.shift;
+  return ir2 * ir6 * (6.0 * pc.b - 12.0 * pc.a * ir6);
+}
+template <>
+__device__ inline float pair_g<TS_MORSE, float>(const PairCoef &pc, float r2t, double, float *phi, bool want_phi) {
+  const float r = sqrtf(r2t);
+  const float x = expf(-(float)pc.b * (r - (float)pc.c));
+  const float D = (float)pc.a;
+  if (want_phi) *phi = D * (x * x - 2.0f * x) - (float)pc.shift;
+  return 2.0f * (float)pc.b * D * (x - x * x) / r;
+}
+template <>
+__device__ inline double pair_g<TS_MORSE, double>(const PairCoef &pc, double r2t, double, double *phi,
+                                                  bool want_phi) {
+  const double r = sqrt(r2t);
+  const double x = exp(-pc.b * (r - pc.c));
+  if (want_phi) *phi = pc.a * (x * x - 2.0 * x) - pc.shift;
+  return 2.0 * pc.b * pc.a * (x - x * x) / r;
+}
+template <>
+__device__ inline float pair_g<TS_SOFT_SPHERE, float>(const PairCoef &pc, float r2t, double r2, float *phi,
+                                                      bool want_phi) {
+  // overlap 1 - r/sigma in float64: it cancels catastrophically near contact
+  const double r64 = sqrt(r2);
+  const float u = (float)(1.0 - r64 * pc.c);
+  const float eps = (float)pc.a;
+  if (want_phi) *phi = 0.5f * eps * u * u;
+  return -eps * (float)pc.c * u / (float)r64;
+}
+template <>
+__device__ inline double pair_g<TS_SOFT_SPHERE, double>(const PairCoef &pc, double, double r2, double *phi,
+                                                        bool want_phi) {
+  const double r = sqrt(r2);
+  const double u = 1.0 - r * pc.c;
+  if (want_phi) *phi = 0.5 * pc.a * u * u;
+  return -pc.a * pc.c * u / r;
+}
+
+// Second-derivative data for the adjoint: returns g = phi'/r and h = phi''(r); all in T.
+template <int KIND, typename T>
+__device__ inline void pair_g_h(const PairCoef &pc, T r2t, double r2, T *g, T *h);
+
+template <>
+__device__ inline void pair_g_h<TS_LJ, float>(const PairCoef &pc, float r2t, double, float *g, float *h) {
+  const float ir2 = 1.0f / r2t;
+  const float ir6 = ir2 * ir2 * ir2;
+  const float a = (float)pc.a, b = (float)pc.b;
+  *g = ir2 * ir6 * (6.0f * b - 12.0f * a * ir6);
+  *h = ir2 * ir6 * (156.0f * a * ir6 - 42.0f * b);
+}
+template <>
+__device__ inline void pair_g_h<TS_LJ, double>(const PairCoef &pc, double r2t, double, double *g, double *h) {
+  const double ir2 = 1.0 / r2t;
+  const double ir6 = ir2 * ir2 * ir2;
+  *g = ir2 * ir6 * (6.0 * pc.b - 12.0 * pc.a * ir6);
+  *h = ir2 * ir6 * (156.0 * pc.a * ir6 - 42.0 * pc.b);
+}
+template <>
+__device__ inline void pair_g_h<TS_MORSE, float>(const PairCoef &pc, float r2t, double, float *g, float *h) {
+  const float r = sqrtf(r2t);
+  const float al = (float)pc.b, D = (float)pc.a;
+  const float x = expf(-al * (r - (float)pc.c));
+  *g = 2.0f * al * D * (x - x * x) / r;
+  *h = 2.0f * al * al * D * (2.0f * x * x - x);
+}
+template <>
+__device__ inline void pair_g_h<TS_MORSE, double>(const PairCoef &pc, double r2t, double, double *g, double *h) {
+  const double r = sqrt(r2t);
+  const double x = exp(-pc.b * (r - pc.c));
+  *g = 2.0 * pc.b * pc.a * (x - x * x) / r;
+  *h = 2.0 * pc.b * pc.b * pc.a * (2.0 * x * x - x);
+}
+template <>
+__device__ inline void pair_g_h<TS_SOFT_SPHERE, float>(const PairCoef &pc, float, double r2, float *g, float *h) {
+  const double r64 = sqrt(r2);
+  const float u = (float)(1.0 - r64 * pc.c);
+  *g = -(float)pc.a * (float)pc.c * u / (float)r64;
+  *h = (float)(pc.a * pc.c * pc.c);
+}
+template <>
+__device__ inline void pair_g_h<TS_SOFT_SPHERE, double>(const PairCoef &pc, double, double r2, double *g,
+                                                        double *h) {
+  const double r = sqrt(r2);
+  const double u = 1.0 - r * pc.c;
+  *g = -pc.a * pc.c * u / r;
+  *h = pc.a * pc.c * pc.c;
+}
+
+// Derivatives of g = phi'/r with respect to the raw parameter triple (float64).
+template <int KIND>
+__device__ inline void pair_dg_dparams(const PairCoef &pc, double r2, double out[3]);
+
+template <>
+__device__ inline void pair_dg_dparams<TS_LJ>(const PairCoef &pc, double r2, double out[3]) {
+  const double eps = pc.raw[0], sig = pc.raw[1];
+  const double s2 = sig * sig / r2;
+  const double sr6 = s2 * s2 * s2;
+  const double sr12 = sr6 * sr6;
+  const double g = 24.0 * eps / r2 * (sr6 - 2.0 * sr12);
+  out[0] = g / eps;
+  out[1] = 24.0 * eps / r2 * (6.0 * sr6 - 24.0 * sr12) / sig;
+  out[2] = 0.0;
+}
+template <>
+__device__ inline void pair_dg_dparams<TS_MORSE>(const PairCoef &pc, double r2, double out[3]) {
+  const double D = pc.raw[0], al = pc.raw[1], r0 = pc.raw[2];
+  const double r = sqrt(r2);
+  const double x = exp(-al * (r - r0));
+  out[0] = 2.0 * al * (x - x * x) / r;
+  out[1] = (2.0 * D * (x - x * x) + 2.0 * al * D * (1.0 - 2.0 * x) * (-(r - r0) * x)) / r;
+  out[2] = 2.0 * al * D * (1.0 - 2.0 * x) * (al * x) / r;
+}
+template <>
+__device__ inline void pair_dg_dparams<TS_SOFT_SPHERE>(const PairCoef &pc, double r2, double out[3]) {
+  const double eps = pc.raw[0], sig = pc.raw[1];
+  const double r = sqrt(r2);
+  const double u = 1.0 - r / sig;
+  out[0] = -u / sig / r;
+  out[1] = (eps / (sig * sig) - 2.0 * eps * r / (sig * sig * sig)) / r;
+  out[2] = 0.0;
+}
+
+// ----------------------------------------------------------------------------- reductions
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Add the NV per-lane values v[k] into out[s * out_stride + k].  Must be reached by every lane of
+// the wavefront (convergent control flow).  One atomic per value and wavefront when all valid lanes
+// share a system (the common case: systems are contiguous), one per lane otherwise.
+template <int NV>
+__device__ inline void add_by_system(double *out, int out_stride, int s, bool valid, const double (&v)[NV]) {
+  const uint64_t act = __ballot(valid);
+  if (act == 0) return;
+  const int first = __ffsll((unsigned long long)act) - 1;
+  const int s_first = __shfl(s, first, kWave);
+  if (__all(!valid || s == s_first)) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double t = wave_sum(valid ? v[k] : 0.0);
+      if ((int)__lane_id() == first) atomicAdd(&out[(int64_t)s_first * out_stride + k], t);
+    }
+  } else if (valid) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) atomicAdd(&out[(int64_t)s * out_stride + k], v[k]);
+  }
+}
+
+// Fill kernel (used instead of hipMemsetAsync so that calls remain safe inside captured graphs).
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+inline int fill_async(T *p, int64_t n, T v, hipStream_t st) {
+  if (n <= 0 || p == nullptr) return TS_OK;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, p, n, v);
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+}  // namespace ts

@@ -1,0 +1,37 @@
+// Neighbor-list workspace layout and the update routine used by the step loops.
+#pragma once
+
+#include "ts_internal.h"
+
+namespace ts {
+
+// Bin geometry of one system at its last build.
+struct NlGeom {
+  double inv[9];    // cell^-1 (row convention: s = r inv)
+  double reach[3];  // r_list / w_k  (w_k perpendicular width)
+  int n[3];         // bins along each direction
+  int m[3];         // stencil half-width in bins
+  int active;       // rebuilt by the current update
+  int pad;
+};
+
+// Views into the caller's workspace.  Bins of system s start at 2 sys_offsets[s] + s (at most
+// 2 N_s + 1 bins per system).
+struct NlWork {
+  NlGeom *geom;
+  int32_t *flags;     // [S] rebuild requests
+  int32_t *atom_bin;  // [N] local bin of each atom
+  int32_t *atom_img;  // [N] packed integer image offset floor(s) of each atom
+  int32_t *count;     // [2N+S] atoms per bin
+  int32_t *start;     // [2N+S] first slot of each bin in perm (global atom index space)
+  int32_t *fill;      // [2N+S] scatter cursors
+  int32_t *perm;      // [N] atoms sorted by (system, bin, index)
+  size_t bytes;
+};
+
+NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys);
+
+// Enqueue the device-side validity test (force = 0) and the rebuild of the flagged systems.
+int nl_update(const ts_batch *b, ts_neighbor_list *nl, int force, int64_t max_atoms, hipStream_t st);
+
+}  // namespace ts

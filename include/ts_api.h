@@ -101,8 +101,10 @@ typedef struct {
 } ts_pair_params;
 
 /* Neighbor list: padded per-atom rows.  Entry k of atom i is nbr[k * stride + i] for
-   k < n_nbr[i] <= max_nbr, packed as  j_local | (S0+16) << 17 | (S1+16) << 22 | (S2+16) << 27
+   k < n_nbr[i] <= max_nbr, packed as  j_local << 15 | (S0+16) << 10 | (S1+16) << 5 | (S2+16)
    with j_local = j - sys_offsets[system of i] (so each system may hold up to 2^17 atoms).
+   Rows are sorted by the unsigned entry value, i.e. by (j_local, S0, S1, S2): every builder
+   produces the same row for the same pair set. 
    A list built at (ref_pos, ref_cell) with list radius r_list = cutoff + skin holds every (j, S)
    with |d| < r_list (float64 test), j != i or S != 0, and stays valid while
    2 max_i |r_i - ref_i M| + r_list ||M - I||_F <= skin, M = ref_cell^-1 cell (M = I when the
@@ -115,7 +117,8 @@ typedef struct {
                           adjoint entry points require half = 0 */
   int32_t max_nbr;     /* per-atom capacity (rows of nbr) */
   int32_t bin_factor;  /* cell-list bins per list radius along each direction (1..4) */
-  int32_t reserved;
+  int32_t lanes_per_atom; /* lanes of a wavefront sharing one atom's row in the fused step
+                             kernels: 1, 2, 4 or 8 (0 = 4) */
   int32_t *nbr;        /* device [max_nbr][stride] */
   int32_t *n_nbr;      /* device [N] */
   double *ref_pos;     /* device SoA [3][stride]: positions at the last build of each system */
@@ -134,8 +137,8 @@ size_t ts_neighbor_workspace_bytes(int64_t n_atoms, int64_t n_systems);
    s = r cell^-1 (float64) wrapped to [0, 1); n_k = max(1, floor(bin_factor w_k / r_list)) bins
    along direction k (w_k the perpendicular width), reduced until a system has at most 2 N_s + 1
    bins; every bin within reach (stencil ceil(r_list n_k / w_k), several images of one bin when
-   the cell is narrower than 2 r_list) is searched.  Entries of a row are ordered by stencil
-   position then atom index, so a list is a deterministic function of positions and cells.
+   the cell is narrower than 2 r_list) is searched.  Rows are in the canonical sorted order, so a
+   list is a deterministic function of positions and cells.
    Errors: TS_E_INVALID (null pointers, sizes, cutoff <= 0, skin < 0, max_nbr < 1,
    workspace too small), TS_E_CAPACITY (a system above TS_MAX_SYSTEM_ATOMS). */
 int ts_neighbor_build(const ts_batch *batch, ts_neighbor_list *nl, int32_t force, ts_stream_t stream);

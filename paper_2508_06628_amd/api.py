@@ -118,8 +118,10 @@ def pair_params_from_spec(spec, prec: str = "f32") -> N.TsPairParams:
 class NeighborList:
     """Padded neighbor list of a batch (rows [max_nbr][N] of packed (j, S) entries)."""
 
-    def __init__(self, batch: Batch, cutoff: float, skin: float, max_nbr: int, bin_factor: int = 1, half: bool = False):
+    def __init__(self, batch: Batch, cutoff: float, skin: float, max_nbr: int, bin_factor: int = 1, half: bool = False,
+                 lanes_per_atom: int = 0):
         self.cutoff, self.skin, self.half, self.bin_factor = float(cutoff), float(skin), bool(half), int(bin_factor)
+        self.lanes_per_atom = int(lanes_per_atom)
         self.n_atoms, self.n_systems = batch.n_atoms, batch.n_systems
         self._alloc(batch, int(max_nbr))
 
@@ -142,6 +144,7 @@ class NeighborList:
         s.half = 1 if self.half else 0
         s.max_nbr = self.max_nbr
         s.bin_factor = self.bin_factor
+        s.lanes_per_atom = self.lanes_per_atom
         s.nbr = self.nbr.data_ptr()
         s.n_nbr = self.n_nbr.data_ptr()
         s.ref_pos = self.ref_pos.data_ptr()
@@ -164,8 +167,8 @@ class NeighborList:
             if sel.size == 0:
                 break
             e = nbr[k, sel]
-            rows.append((sel, (e & 0x1FFFF).astype(np.int64), ((e >> 17) & 31).astype(np.int64) - 16,
-                         ((e >> 22) & 31).astype(np.int64) - 16, ((e >> 27) & 31).astype(np.int64) - 16))
+            rows.append((sel, (e >> 15).astype(np.int64), ((e >> 10) & 31).astype(np.int64) - 16,
+                         ((e >> 5) & 31).astype(np.int64) - 16, (e & 31).astype(np.int64) - 16))
         if not rows:
             z = np.zeros(0, np.int64)
             return z, z, z, z, z
@@ -180,10 +183,10 @@ def estimate_max_nbr(batch: Batch, r_list: float, margin: float = 1.3) -> int:
 
 
 def build_neighbor_list(batch: Batch, cutoff: float, skin: float, bin_factor: int = 1, max_nbr: Optional[int] = None,
-                        margin: float = 1.25, half: bool = False) -> NeighborList:
+                        margin: float = 1.25, half: bool = False, lanes_per_atom: int = 0) -> NeighborList:
     """Allocate and build a list, regrowing once if the first capacity guess was too small."""
     guess = max_nbr or estimate_max_nbr(batch, cutoff + skin)
-    nl = NeighborList(batch, cutoff, skin, guess, bin_factor, half)
+    nl = NeighborList(batch, cutoff, skin, guess, bin_factor, half, lanes_per_atom)
     ts_neighbor_build(batch, nl, force=True)
     st = nl.read_status()
     if st[N.TS_STATUS_NONFINITE] or st[N.TS_STATUS_SHIFT]:

@@ -35,6 +35,8 @@ __global__ void k_adj_drift(int64_t n, int64_t st, const double *__restrict__ lr
 template <int KIND, typename T, bool SINGLE>
 __global__ void __launch_bounds__(256) k_pair_vjp(AdjArgs a, PairTable tab) {
   __shared__ double acc[TS_MAX_SPECIES * TS_MAX_SPECIES * 3];
+  __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
+  if (!SINGLE) table_to_lds(tab, ltab);
   if (!SINGLE) {
     for (int k = threadIdx.x; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += blockDim.x) acc[k] = 0.0;
     __syncthreads();
@@ -58,13 +60,13 @@ __global__ void __launch_bounds__(256) k_pair_vjp(AdjArgs a, PairTable tab) {
       const uint32_t ent = a.nbr[(int64_t)k * st + i];
       const int64_t j = a0 + entry_j(ent);
       const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
-      const double dx = (a.pos[j] - rx) + (S0 * h[0] + S1 * h[3] + S2 * h[6]);
-      const double dy = (a.pos[st + j] - ry) + (S0 * h[1] + S1 * h[4] + S2 * h[7]);
-      const double dz = (a.pos[2 * st + j] - rz) + (S0 * h[2] + S1 * h[5] + S2 * h[8]);
-      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h[0], h[3], h[6]);
+      const double dy = shift_comp(a.pos[st + j] - ry, S0, S1, S2, h[1], h[4], h[7]);
+      const double dz = shift_comp(a.pos[2 * st + j] - rz, S0, S1, S2, h[2], h[5], h[8]);
+      const double r2 = norm2(dx, dy, dz);
       if (!(r2 < tab.cut2)) continue;
       const int sj = (SINGLE || a.species == nullptr) ? 0 : a.species[j];
-      const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : tab.c[si * TS_MAX_SPECIES + sj];
+      const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : ltab[si * TS_MAX_SPECIES + sj];
       if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
       const double scj = a.mass ? a.accel / a.mass[j] : a.accel;
       const double dux = scj * a.lv[j] - uix, duy = scj * a.lv[st + j] - uiy, duz = scj * a.lv[2 * st + j] - uiz;
@@ -161,10 +163,10 @@ __global__ void __launch_bounds__(256) k_rdf_hist(RdfArgs a, double *g) {
       const uint32_t ent = a.nbr[(int64_t)k * st + i];
       const int64_t j = a0 + entry_j(ent);
       const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
-      const double dx = (a.pos[j] - rx) + (S0 * h[0] + S1 * h[3] + S2 * h[6]);
-      const double dy = (a.pos[st + j] - ry) + (S0 * h[1] + S1 * h[4] + S2 * h[7]);
-      const double dz = (a.pos[2 * st + j] - rz) + (S0 * h[2] + S1 * h[5] + S2 * h[8]);
-      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h[0], h[3], h[6]);
+      const double dy = shift_comp(a.pos[st + j] - ry, S0, S1, S2, h[1], h[4], h[7]);
+      const double dz = shift_comp(a.pos[2 * st + j] - rz, S0, S1, S2, h[2], h[5], h[8]);
+      const double r2 = norm2(dx, dy, dz);
       if (!(r2 < a.rmax2)) continue;
       const double r = sqrt(r2);
       int b0 = (int)floor((r - span) / a.dr - 0.5);
@@ -237,10 +239,10 @@ __global__ void __launch_bounds__(256) k_rdf_vjp(RdfArgs a, const double *dl_dg,
     const uint32_t ent = a.nbr[(int64_t)k * st + i];
     const int64_t j = a0 + entry_j(ent);
     const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
-    const double dx = (a.pos[j] - rx) + (S0 * h[0] + S1 * h[3] + S2 * h[6]);
-    const double dy = (a.pos[st + j] - ry) + (S0 * h[1] + S1 * h[4] + S2 * h[7]);
-    const double dz = (a.pos[2 * st + j] - rz) + (S0 * h[2] + S1 * h[5] + S2 * h[8]);
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h[0], h[3], h[6]);
+    const double dy = shift_comp(a.pos[st + j] - ry, S0, S1, S2, h[1], h[4], h[7]);
+    const double dz = shift_comp(a.pos[2 * st + j] - rz, S0, S1, S2, h[2], h[5], h[8]);
+    const double r2 = norm2(dx, dy, dz);
     if (!(r2 < a.rmax2)) continue;
     const double r = sqrt(r2);
     int b0 = (int)floor((r - span) / a.dr - 0.5);

@@ -12,6 +12,8 @@ namespace ts {
 
 template <int KIND, typename T, bool EV, bool SINGLE>
 __global__ void __launch_bounds__(256) k_pair_forces(ForceArgs a, PairTable tab) {
+  __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
+  if (!SINGLE) table_to_lds(tab, ltab);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = i < a.n;
   const int64_t ii = valid ? i : 0;
@@ -29,17 +31,17 @@ __global__ void __launch_bounds__(256) k_pair_forces(ForceArgs a, PairTable tab)
     const int si = (SINGLE || a.species == nullptr) ? 0 : a.species[ii];
     const int nn = a.n_nbr[ii];
     const double cut2 = tab.cut2;
-    PairCoef pc0 = tab.c[0];
+    const PairCoef pc0 = tab.c[0];
     for (int k = 0; k < nn; ++k) {
       const uint32_t ent = a.nbr[(int64_t)k * st + ii];
       const int64_t j = a0 + entry_j(ent);
       const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
-      const double dx = (a.pos[j] - rx) + (S0 * h00 + S1 * h10 + S2 * h20);
-      const double dy = (a.pos[st + j] - ry) + (S0 * h01 + S1 * h11 + S2 * h21);
-      const double dz = (a.pos[2 * st + j] - rz) + (S0 * h02 + S1 * h12 + S2 * h22);
-      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h00, h10, h20);
+      const double dy = shift_comp(a.pos[st + j] - ry, S0, S1, S2, h01, h11, h21);
+      const double dz = shift_comp(a.pos[2 * st + j] - rz, S0, S1, S2, h02, h12, h22);
+      const double r2 = norm2(dx, dy, dz);
       if (!(r2 < cut2)) continue;
-      const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : tab.c[si * TS_MAX_SPECIES + a.species[j]];
+      const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : ltab[si * TS_MAX_SPECIES + a.species[j]];
       if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
       const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
       T phi = (T)0;

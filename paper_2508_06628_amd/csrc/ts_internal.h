@@ -47,14 +47,22 @@ int validate_list(const ts_batch *b, const ts_neighbor_list *nl);
 
 // ----------------------------------------------------------------------------- list entries
 
+// List entry: j_local in bits 15..31 and each image component S_k + 16 in a 5-bit field, so that the
+// unsigned order of entries is the lexicographic order of (j_local, S0, S1, S2).
 __host__ __device__ inline uint32_t pack_entry(int j_local, int s0, int s1, int s2) {
-  return (uint32_t)j_local | ((uint32_t)(s0 + 16) << 17) | ((uint32_t)(s1 + 16) << 22) |
-         ((uint32_t)(s2 + 16) << 27);
+  return ((uint32_t)j_local << 15) | ((uint32_t)(s0 + 16) << 10) | ((uint32_t)(s1 + 16) << 5) | (uint32_t)(s2 + 16);
 }
-__device__ inline int entry_j(uint32_t e) { return (int)(e & 0x1FFFFu); }
-__device__ inline int entry_s0(uint32_t e) { return (int)((e >> 17) & 31u) - 16; }
-__device__ inline int entry_s1(uint32_t e) { return (int)((e >> 22) & 31u) - 16; }
-__device__ inline int entry_s2(uint32_t e) { return (int)((e >> 27) & 31u) - 16; }
+__device__ inline int entry_j(uint32_t e) { return (int)(e >> 15); }
+__device__ inline int entry_s0(uint32_t e) { return (int)((e >> 10) & 31u) - 16; }
+__device__ inline int entry_s1(uint32_t e) { return (int)((e >> 5) & 31u) - 16; }
+__device__ inline int entry_s2(uint32_t e) { return (int)(e & 31u) - 16; }
+
+// Pair vector component d_c = (r_j,c - r_i,c) + S @ cell (column c), written with explicit fused
+// multiply-adds so that every kernel evaluates it, and |d|^2, with the same rounding.
+__device__ inline double shift_comp(double dr, double S0, double S1, double S2, double h0c, double h1c, double h2c) {
+  return dr + fma(S2, h2c, fma(S1, h1c, S0 * h0c));
+}
+__device__ inline double norm2(double dx, double dy, double dz) { return fma(dz, dz, fma(dy, dy, dx * dx)); }
 
 // ----------------------------------------------------------------------------- pair tables
 
@@ -76,6 +84,16 @@ struct PairTable {
 };
 
 PairTable make_table(const ts_pair_params *pp);
+
+// Copy the species-pair table into LDS using static indices only: indexing a by-value kernel
+// argument with a run-time index makes the compiler keep a private (scratch) copy per lane.
+// Must be reached by every thread of the workgroup.
+__device__ inline void table_to_lds(const PairTable &t, PairCoef *dst) {
+#pragma unroll
+  for (int k = 0; k < TS_MAX_SPECIES * TS_MAX_SPECIES; ++k)
+    if ((int)threadIdx.x == k) dst[k] = t.c[k];
+  __syncthreads();
+}
 
 // Pair function: returns g = phi'(r)/r and (optionally) phi(r) - shift.  d is the pair vector in
 // the pair precision, r2 its squared norm (float64) for masks and the soft-sphere overlap.

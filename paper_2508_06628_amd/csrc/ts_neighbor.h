@@ -26,6 +26,8 @@ struct NlWork {
   int32_t *start;     // [2N+S] first slot of each bin in perm (global atom index space)
   int32_t *fill;      // [2N+S] scatter cursors
   int32_t *perm;      // [N] atoms sorted by (system, bin, index)
+  double *pos_alt;    // [3][N] second position buffer of the fused step loop
+  int32_t *flags3;    // fused step loop: rebuild flags [3][S], flagged lists [3][S], counts [3]
   size_t bytes;
 };
 

@@ -5,9 +5,11 @@
 // with the integer image offset kept per atom; a counting sort by bin (stable: each bin's atoms
 // are sorted by index); then each atom scans the bins within reach along every direction (a
 // bin may be visited under several lattice images when the cell is narrower than 2 r_list),
-// tests |d|^2 < r_list^2 in float64 and appends (j, S) to its padded row.
+// tests |d|^2 < r_list^2 in float64 and appends (j, S) to its padded row, which is finally sorted
+// into the canonical (j, S0, S1, S2) order.
 #include "ts_internal.h"
 #include "ts_neighbor.h"
+#include "ts_step.h"
 
 namespace ts {
 
@@ -52,38 +54,12 @@ __global__ void k_nl_trigger(int64_t n, int64_t stride, const int32_t *__restric
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int s = sys_idx[i];
-  const double *h = cell + 9 * (int64_t)s;
-  const double *h0 = ref_cell + 9 * (int64_t)s;
-  bool same = true;
+  double r[3];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) same &= (h[k] == h0[k]);
-  double r[3], r0[3], dlt[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    r[c] = pos[c * stride + i];
-    r0[c] = ref_pos[c * stride + i];
-  }
-  double strain = 0.0;
-  if (same) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) dlt[c] = r[c] - r0[c];
-  } else {
-    double hi[9], M[9];
-    inv3(h0, hi, det3(h0));
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) M[3 * a + b] = hi[3 * a] * h[b] + hi[3 * a + 1] * h[3 + b] + hi[3 * a + 2] * h[6 + b];
-    double acc = 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        const double e = M[3 * a + b] - (a == b ? 1.0 : 0.0);
-        acc += e * e;
-      }
-    strain = sqrt(acc);
-    for (int c = 0; c < 3; ++c) dlt[c] = r[c] - (r0[0] * M[c] + r0[1] * M[3 + c] + r0[2] * M[6 + c]);
-  }
-  const double dm = sqrt(dlt[0] * dlt[0] + dlt[1] * dlt[1] + dlt[2] * dlt[2]);
-  const double lhs = 2.0 * dm + r_list * strain;
-  if (!(lhs <= skin)) flags[s] = 1;  // also catches NaN, which the build then reports
+  for (int c = 0; c < 3; ++c) r[c] = pos[c * stride + i];
+  // also true for a non-finite position, which the build then reports
+  if (list_invalid(r, ref_pos, stride, i, cell + 9 * (int64_t)s, ref_cell + 9 * (int64_t)s, skin, r_list))
+    flags[s] = 1;
 }
 
 // One thread per system: bin geometry of the systems to rebuild.
@@ -331,8 +307,8 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
           double d[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            d[c] = (pos[c * stride + j] - r[c]) + (S0 * h[c] + S1 * h[3 + c] + S2 * h[6 + c]);
-          const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            d[c] = shift_comp(pos[c * stride + j] - r[c], (double)S0, (double)S1, (double)S2, h[c], h[3 + c], h[6 + c]);
+          const double r2 = norm2(d[0], d[1], d[2]);
           if (!(r2 < rl2)) continue;
           if (half) {
             const int first = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
@@ -349,7 +325,18 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
       }
     }
   }
-  n_nbr[i] = cnt < max_nbr ? cnt : max_nbr;
+  // canonical row order: ascending packed entry = lexicographic (j, S0, S1, S2)
+  const int nw = cnt < max_nbr ? cnt : max_nbr;
+  for (int a = 1; a < nw; ++a) {
+    const uint32_t key = nbr[(int64_t)a * stride + i];
+    int q = a - 1;
+    while (q >= 0 && nbr[(int64_t)q * stride + i] > key) {
+      nbr[(int64_t)(q + 1) * stride + i] = nbr[(int64_t)q * stride + i];
+      --q;
+    }
+    nbr[(int64_t)(q + 1) * stride + i] = key;
+  }
+  n_nbr[i] = nw;
   atomicMax((unsigned long long *)&status[TS_STATUS_MAX_NBR], (unsigned long long)cnt);
   if (cnt > max_nbr) atomicMax((unsigned long long *)&status[TS_STATUS_OVERFLOW], 1ull);
   if (shift_bad) atomicMax((unsigned long long *)&status[TS_STATUS_SHIFT], 1ull);
@@ -374,6 +361,8 @@ NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   w.start = reinterpret_cast<int32_t *>(take(4 * nbins));
   w.fill = reinterpret_cast<int32_t *>(take(4 * nbins));
   w.perm = reinterpret_cast<int32_t *>(take(4 * (n_atoms + 1)));
+  w.pos_alt = reinterpret_cast<double *>(take(24 * (n_atoms + 1)));
+  w.flags3 = reinterpret_cast<int32_t *>(take(4 * (6 * n_sys + 8)));
   w.bytes = static_cast<size_t>(p - static_cast<char *>(ws));
   return w;
 }

@@ -5,10 +5,20 @@
 #include <mutex>
 #include <vector>
 
+#include <cstdlib>
+
 #include "ts_forces.h"
 #include "ts_neighbor.h"
+#include "ts_step.h"
 
 namespace ts {
+
+// TS_NVE_UNFUSED=1 selects the multi-kernel step (separate list update, force and kick launches)
+// instead of the fused one; both compute the same trajectory.
+static bool fused_enabled() {
+  const char *e = std::getenv("TS_NVE_UNFUSED");
+  return !(e && e[0] == '1');
+}
 
 // v += (dt/2) a F / m ; r += dt v
 template <typename T>
@@ -20,9 +30,9 @@ __global__ void k_vv_kick_drift(int64_t n, int64_t st, double *__restrict__ pos,
   const double sc = mass ? accel / mass[i] : accel;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double v = vel[c * st + i] + (half_dt * (double)F[c * st + i]) * sc;
+    const double v = fma(half_dt * (double)F[c * st + i], sc, vel[c * st + i]);
     vel[c * st + i] = v;
-    pos[c * st + i] = pos[c * st + i] + dt * v;
+    pos[c * st + i] = fma(dt, v, pos[c * st + i]);
   }
 }
 
@@ -34,7 +44,7 @@ __global__ void k_vv_kick(int64_t n, int64_t st, double *__restrict__ vel, const
   if (i >= n) return;
   const double sc = mass ? accel / mass[i] : accel;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) vel[c * st + i] = vel[c * st + i] + (half_dt * (double)F[c * st + i]) * sc;
+  for (int c = 0; c < 3; ++c) vel[c * st + i] = fma(half_dt * (double)F[c * st + i], sc, vel[c * st + i]);
 }
 
 // ekin[s] += 1/2 m |v|^2 / accel
@@ -104,10 +114,83 @@ static int nve_sequence_t(const ts_batch *b, ts_neighbor_list *nl, const PairTab
   return TS_OK;
 }
 
+// One launch per step (see ts_step.hip): systems of at most kLdsMaxAtoms atoms, full list.
+static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable &tab, int prec, double dt,
+                              double accel, int n_steps, void *force, double *epot, double *ekin, double *virial,
+                              int64_t max_atoms, hipStream_t st) {
+  const int64_t n = b->n_atoms, S = b->n_systems;
+  NlWork w = nl_work(nl->workspace, n, S);
+  const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : 4;
+  int rc = fill_async<int32_t>(w.flags3, 6 * S + 8, 0, st);
+  if (rc != TS_OK) return rc;
+  if (epot) {
+    rc = fill_async<double>(epot, S, 0.0, st);
+    if (rc != TS_OK) return rc;
+  }
+  if (virial) {
+    rc = fill_async<double>(virial, 9 * S, 0.0, st);
+    if (rc != TS_OK) return rc;
+  }
+  double *buf[2] = {b->pos, w.pos_alt};
+  const int64_t sts[2] = {stride_of(b), n};
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.offs = b->sys_offsets;
+  a.vel = b->vel;
+  a.st_vel = stride_of(b);
+  a.mass = b->mass;
+  a.species = b->species;
+  a.cell = b->cell;
+  a.force = force;
+  a.nbr = reinterpret_cast<uint32_t *>(nl->nbr);
+  a.n_nbr = nl->n_nbr;
+  a.max_nbr = nl->max_nbr;
+  a.half = nl->half;
+  a.ref_pos = nl->ref_pos;
+  a.ref_cell = nl->ref_cell;
+  a.status = nl->status;
+  a.r_list = nl->cutoff + nl->skin;
+  a.skin = nl->skin;
+  a.half_dt = 0.5 * dt;
+  a.dt = dt;
+  a.accel = accel;
+  for (int step = 0; step <= n_steps; ++step) {
+    const int mode = step == 0 ? kStepFirst : (step == n_steps ? kStepLast : kStepMid);
+    a.pos_in = buf[step % 2];
+    a.st_in = sts[step % 2];
+    a.pos_out = buf[(step + 1) % 2];
+    a.st_out = sts[(step + 1) % 2];
+    a.flag_cur = w.flags3 + S * (step % 3);
+    a.flag_next = w.flags3 + S * ((step + 1) % 3);
+    a.flag_clear = w.flags3 + S * ((step + 2) % 3);
+    a.list_cur = w.flags3 + 3 * S + S * (step % 3);
+    a.list_next = w.flags3 + 3 * S + S * ((step + 1) % 3);
+    a.count_cur = w.flags3 + 6 * S + step % 3;
+    a.count_next = w.flags3 + 6 * S + (step + 1) % 3;
+    a.count_clear = w.flags3 + 6 * S + (step + 2) % 3;
+    a.pos_final = (mode == kStepLast && step % 2 == 1) ? b->pos : nullptr;
+    a.epot = mode == kStepLast ? epot : nullptr;
+    a.virial = mode == kStepLast ? virial : nullptr;
+    if (mode != kStepFirst) {
+      rc = launch_rebuild(a, S, max_atoms, st);
+      if (rc != TS_OK) return rc;
+    }
+    rc = launch_step(mode, tl, a, tab, prec, S, max_atoms, st);
+    if (rc != TS_OK) return rc;
+  }
+  if (ekin) {
+    rc = launch_kinetic(b, accel, ekin, st);
+    if (rc != TS_OK) return rc;
+  }
+  return TS_OK;
+}
+
 static int nve_sequence(const ts_batch *b, ts_neighbor_list *nl, const ts_pair_params *pp, double dt, double accel,
                         int n_steps, void *force, double *epot, double *ekin, double *virial, int64_t max_atoms,
                         hipStream_t st) {
   const PairTable tab = make_table(pp);
+  if (n_steps >= 1 && b->n_atoms > 0 && max_atoms <= kLdsMaxAtoms && !nl->half && fused_enabled())
+    return nve_fused_sequence(b, nl, tab, pp->prec, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, st);
   if (pp->prec == TS_PAIR_F32)
     return nve_sequence_t<float>(b, nl, tab, pp->prec, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, st);
   return nve_sequence_t<double>(b, nl, tab, pp->prec, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, st);

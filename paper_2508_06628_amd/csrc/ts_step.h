@@ -1,0 +1,93 @@
+// Fused velocity-Verlet step kernels (one launch per step for systems that fit in LDS).
+#pragma once
+
+#include "ts_internal.h"
+
+namespace ts {
+
+constexpr int kStepFirst = 0;  // first half kick and drift (forces given)
+constexpr int kStepMid = 1;    // forces, two half kicks, drift, validity test
+constexpr int kStepLast = 2;   // forces (+ energy, virial), last half kick
+constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)
+
+struct StepArgs {
+  const int64_t *offs;
+  const double *pos_in;  // r_n
+  int64_t st_in;
+  double *pos_out;  // r_{n+1}
+  int64_t st_out;
+  double *pos_final;  // last step: where r_N is copied (the caller's buffer), or null
+  double *vel;        // velocities, forces, list rows and reference positions use st_vel
+  int64_t st_vel;
+  const double *mass;
+  const int32_t *species;
+  const double *cell;
+  void *force;
+  uint32_t *nbr;
+  int32_t *n_nbr;
+  int max_nbr;
+  int half;
+  double *ref_pos;
+  double *ref_cell;
+  int32_t *flag_cur, *flag_next, *flag_clear;  // per-system rebuild flags of steps n, n+1, n+2
+  int32_t *list_cur, *list_next;               // flagged systems of steps n, n+1
+  int32_t *count_cur, *count_next, *count_clear;
+  int64_t *status;
+  double r_list, skin;
+  double half_dt, dt, accel;
+  double *epot, *virial;
+};
+
+// List validity bound of one atom: 2 |r - ref M| + r_list ||M - I||_F > skin, with
+// M = ref_cell^-1 cell, and M = I exactly when the cell is bitwise unchanged.
+__device__ inline bool bound_exceeded(double dm, double strain, double skin, double r_list) {
+  const double lhs = 2.0 * dm + r_list * strain;
+  return !(lhs <= skin);
+}
+
+__device__ inline bool list_invalid(const double r[3], const double *ref_pos, int64_t st, int64_t i, const double *h,
+                                    const double *h0, double skin, double r_list) {
+  bool same = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) same &= (h[k] == h0[k]);
+  double r0[3], dlt[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r0[c] = ref_pos[c * st + i];
+  double strain = 0.0;
+  if (same) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dlt[c] = r[c] - r0[c];
+  } else {
+    const double det = h0[0] * (h0[4] * h0[8] - h0[5] * h0[7]) - h0[1] * (h0[3] * h0[8] - h0[5] * h0[6]) +
+                       h0[2] * (h0[3] * h0[7] - h0[4] * h0[6]);
+    const double id = 1.0 / det;
+    double hi[9], M[9];
+    hi[0] = (h0[4] * h0[8] - h0[5] * h0[7]) * id;
+    hi[1] = (h0[2] * h0[7] - h0[1] * h0[8]) * id;
+    hi[2] = (h0[1] * h0[5] - h0[2] * h0[4]) * id;
+    hi[3] = (h0[5] * h0[6] - h0[3] * h0[8]) * id;
+    hi[4] = (h0[0] * h0[8] - h0[2] * h0[6]) * id;
+    hi[5] = (h0[2] * h0[3] - h0[0] * h0[5]) * id;
+    hi[6] = (h0[3] * h0[7] - h0[4] * h0[6]) * id;
+    hi[7] = (h0[1] * h0[6] - h0[0] * h0[7]) * id;
+    hi[8] = (h0[0] * h0[4] - h0[1] * h0[3]) * id;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) M[3 * p + q] = hi[3 * p] * h[q] + hi[3 * p + 1] * h[3 + q] + hi[3 * p + 2] * h[6 + q];
+    double acc = 0.0;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        const double e = M[3 * p + q] - (p == q ? 1.0 : 0.0);
+        acc += e * e;
+      }
+    strain = sqrt(acc);
+    for (int c = 0; c < 3; ++c) dlt[c] = r[c] - (r0[0] * M[c] + r0[1] * M[3 + c] + r0[2] * M[6 + c]);
+  }
+  return bound_exceeded(sqrt(norm2(dlt[0], dlt[1], dlt[2])), strain, skin, r_list);
+}
+
+int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st);
+
+int launch_step(int mode, int tl, const StepArgs &a, const PairTable &t, int prec, int64_t n_sys, int64_t max_atoms,
+                hipStream_t st);
+
+}  // namespace ts

@@ -1,0 +1,393 @@
+// Fused velocity-Verlet step loop for batches whose systems fit in LDS: two launches per step.
+//
+// k_rebuild_rows (before step n): rebuilds the neighbor rows of the systems flagged at the end of
+//   step n-1.  The flagged systems come as a device-side list, so the launch has no work and exits
+//   at once when nothing was flagged.  A workgroup stages one system's positions in LDS and each
+//   wavefront builds the row of one atom: its 64 lanes test 64 candidate atoms at a time under every
+//   lattice image in reach, and the per-lane counts are combined with a wavefront prefix sum, so
+//   the row comes out in the canonical (j, S0, S1, S2) order without a sort.
+// k_step (step n): a workgroup owns APB = 256/TL atoms of one system (TL lanes per atom); it stages
+//   the system's positions r_n in LDS, evaluates the pair forces of its atoms (TL lanes per atom,
+//   reduced across lanes), applies the two half kicks that meet at step n and the drift to r_{n+1}
+//   (written to the other position buffer) and tests the list validity bound for r_{n+1}, appending
+//   the system to the next rebuild list when it is exceeded.
+// Systems never exchange data, so no synchronisation between workgroups is needed beyond the
+// kernel boundaries.
+#include "ts_forces.h"
+#include "ts_neighbor.h"
+#include "ts_step.h"
+
+namespace ts {
+
+// Flag system s for a rebuild before the next step, appending it once to that step's list.
+__device__ inline void flag_system(const StepArgs &a, int s) {
+  if (atomicExch(&a.flag_next[s], 1) == 0) a.list_next[atomicAdd(a.count_next, 1)] = s;
+}
+
+template <int KIND, typename T, int TL, int MODE>
+__global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
+  extern __shared__ double lds[];
+  __shared__ double geo[12];  // cell^-1 (9), reach (3)
+  __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
+  constexpr int APB = 256 / TL;
+  const int s = blockIdx.y;
+  const int64_t a0 = a.offs[s];
+  const int ns = (int)(a.offs[s + 1] - a0);
+  const int first = blockIdx.x * APB;
+  if (first >= ns) return;
+  const int tid = threadIdx.x;
+  const int grp = tid / TL, lane = tid % TL;
+  const int li = first + grp;
+  const bool own = li < ns;
+  const int64_t i = a0 + li;
+  const double *h = a.cell + 9 * (int64_t)s;
+
+  if (MODE == kStepFirst) {
+    // v += dt/2 a F(r_0); r_1 = r_0 + dt v; list validity of r_1 (cell change included)
+    if (own && lane == 0) {
+      const T *F = static_cast<const T *>(a.force);
+      const double sc = a.mass ? a.accel / a.mass[i] : a.accel;
+      double r[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double v = fma(a.half_dt * (double)F[c * a.st_vel + i], sc, a.vel[c * a.st_vel + i]);
+        a.vel[c * a.st_vel + i] = v;
+        r[c] = fma(a.dt, v, a.pos_in[c * a.st_in + i]);
+        a.pos_out[c * a.st_out + i] = r[c];
+      }
+      if (list_invalid(r, a.ref_pos, a.st_vel, i, h, a.ref_cell + 9 * (int64_t)s, a.skin, a.r_list))
+        flag_system(a, s);
+    }
+    return;
+  }
+
+  table_to_lds(tab, ltab);
+  // 1. stage r_n of the whole system
+  double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
+  for (int k = tid; k < ns; k += 256) {
+    lx[k] = a.pos_in[a0 + k];
+    ly[k] = a.pos_in[a.st_in + a0 + k];
+    lz[k] = a.pos_in[2 * a.st_in + a0 + k];
+  }
+  __syncthreads();
+  const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
+               h22 = h[8];
+  const double rx = own ? lx[li] : 0.0, ry = own ? ly[li] : 0.0, rz = own ? lz[li] : 0.0;
+  const uint32_t *nbr = a.nbr;
+  const int64_t st = a.st_vel;  // list, reference positions, velocities and forces share the batch stride
+  const int nn = own ? a.n_nbr[i] : 0;
+
+  // 3. pair forces of this block's atoms, TL lanes per atom
+  constexpr bool EV = MODE == kStepLast;
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+  double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
+  if (own) {
+    const bool single = tab.n_species == 1 || a.species == nullptr;
+    const int si = single ? 0 : a.species[i];
+    const double cut2 = tab.cut2;
+    for (int k = lane; k < nn; k += TL) {
+      const uint32_t ent = nbr[(int64_t)k * st + i];
+      const int j = entry_j(ent);
+      const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
+      const double dx = shift_comp(lx[j] - rx, S0, S1, S2, h00, h10, h20);
+      const double dy = shift_comp(ly[j] - ry, S0, S1, S2, h01, h11, h21);
+      const double dz = shift_comp(lz[j] - rz, S0, S1, S2, h02, h12, h22);
+      const double r2 = norm2(dx, dy, dz);
+      if (!(r2 < cut2)) continue;
+      // coefficients are read from LDS in both cases (a local copy would live in scratch)
+      const PairCoef &pc = ltab[single ? 0 : si * TS_MAX_SPECIES + a.species[a0 + j]];
+      if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
+      const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
+      T phi = (T)0;
+      const T g = pair_g<KIND, T>(pc, (T)r2, r2, &phi, EV);
+      const T gx = g * tx, gy = g * ty, gz = g * tz;
+      fx += (double)gx;
+      fy += (double)gy;
+      fz += (double)gz;
+      if (EV) {
+        e += (double)phi;
+        w0 += (double)(gx * tx);
+        w1 += (double)(gy * ty);
+        w2 += (double)(gz * tz);
+        w3 += (double)(gx * ty);
+        w4 += (double)(gx * tz);
+        w5 += (double)(gy * tz);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < TL; o <<= 1) {
+    fx += __shfl_xor(fx, o, TL);
+    fy += __shfl_xor(fy, o, TL);
+    fz += __shfl_xor(fz, o, TL);
+  }
+
+  // 4. kicks and drift (lane 0 of each atom)
+  if (own && lane == 0) {
+    T *F = static_cast<T *>(a.force);
+    const T Fx = (T)fx, Fy = (T)fy, Fz = (T)fz;
+    const double sc = a.mass ? a.accel / a.mass[i] : a.accel;
+    const double hx = a.half_dt * (double)Fx, hy = a.half_dt * (double)Fy, hz = a.half_dt * (double)Fz;
+    double vx = a.vel[i], vy = a.vel[st + i], vz = a.vel[2 * st + i];
+    // explicit fused multiply-adds: every kick and drift rounds the same way in every kernel
+    vx = fma(hx, sc, vx);
+    vy = fma(hy, sc, vy);
+    vz = fma(hz, sc, vz);
+    if (MODE == kStepMid) {
+      vx = fma(hx, sc, vx);
+      vy = fma(hy, sc, vy);
+      vz = fma(hz, sc, vz);
+      const double nx = fma(a.dt, vx, rx), ny = fma(a.dt, vy, ry), nz = fma(a.dt, vz, rz);
+      a.pos_out[i] = nx;
+      a.pos_out[a.st_out + i] = ny;
+      a.pos_out[2 * a.st_out + i] = nz;
+      // the cell is unchanged since the list was built (a changed cell was flagged by the first step)
+      const double dx = nx - a.ref_pos[i], dy = ny - a.ref_pos[st + i], dz = nz - a.ref_pos[2 * st + i];
+      if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list)) flag_system(a, s);
+    } else {
+      F[i] = Fx;
+      F[st + i] = Fy;
+      F[2 * st + i] = Fz;
+      if (a.pos_final) {
+        a.pos_final[i] = rx;
+        a.pos_final[st + i] = ry;
+        a.pos_final[2 * st + i] = rz;
+      }
+    }
+    a.vel[i] = vx;
+    a.vel[st + i] = vy;
+    a.vel[2 * st + i] = vz;
+  }
+  if (MODE == kStepMid && blockIdx.x == 0 && tid == 0) {
+    a.flag_clear[s] = 0;
+    if (s == 0) *a.count_clear = 0;
+  }
+  if (EV && (a.epot || a.virial)) {
+    // every lane of the block belongs to system s
+    const double ev = wave_sum(0.5 * e);
+    const double v0 = wave_sum(-0.5 * w0), v1 = wave_sum(-0.5 * w1), v2 = wave_sum(-0.5 * w2);
+    const double v3 = wave_sum(-0.5 * w3), v4 = wave_sum(-0.5 * w4), v5 = wave_sum(-0.5 * w5);
+    if ((tid % kWave) == 0) {
+      if (a.epot) atomicAdd(&a.epot[s], ev);
+      if (a.virial) {
+        double *W = a.virial + 9 * (int64_t)s;
+        atomicAdd(&W[0], v0);
+        atomicAdd(&W[4], v1);
+        atomicAdd(&W[8], v2);
+        atomicAdd(&W[1], v3);
+        atomicAdd(&W[3], v3);
+        atomicAdd(&W[2], v4);
+        atomicAdd(&W[6], v4);
+        atomicAdd(&W[5], v5);
+        atomicAdd(&W[7], v5);
+      }
+    }
+  }
+}
+
+// Rebuild rows: one wavefront per atom; a workgroup of 16 wavefronts handles 16 consecutive atoms
+// of one flagged system ("chunks" of 16 atoms; chunks_per_sys covers the largest system).
+constexpr int kRebuildWaves = 16;
+
+__global__ void __launch_bounds__(1024) k_rebuild_rows(StepArgs a, int chunks_per_sys) {
+  extern __shared__ double lds[];
+  __shared__ double geo[12];
+  const int n_flag = *a.count_cur;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const double rl2 = a.r_list * a.r_list;
+  const int64_t st = a.st_vel;
+  for (int chunk = blockIdx.x; chunk < n_flag * chunks_per_sys; chunk += gridDim.x) {
+    const int s = a.list_cur[chunk / chunks_per_sys];
+    const int c0 = (chunk % chunks_per_sys) * kRebuildWaves;
+    const int64_t a0 = a.offs[s];
+    const int ns = (int)(a.offs[s + 1] - a0);
+    if (c0 >= ns) continue;  // uniform over the workgroup
+    const double *h = a.cell + 9 * (int64_t)s;
+    __syncthreads();  // the previous chunk's readers are done with lds and geo
+    double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
+    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+      lx[k] = a.pos_in[a0 + k];
+      ly[k] = a.pos_in[a.st_in + a0 + k];
+      lz[k] = a.pos_in[2 * a.st_in + a0 + k];
+    }
+    if (threadIdx.x == 0) {
+      const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
+                         h[2] * (h[3] * h[7] - h[4] * h[6]);
+      const double id = 1.0 / det;
+      geo[0] = (h[4] * h[8] - h[5] * h[7]) * id;
+      geo[1] = (h[2] * h[7] - h[1] * h[8]) * id;
+      geo[2] = (h[1] * h[5] - h[2] * h[4]) * id;
+      geo[3] = (h[5] * h[6] - h[3] * h[8]) * id;
+      geo[4] = (h[0] * h[8] - h[2] * h[6]) * id;
+      geo[5] = (h[2] * h[3] - h[0] * h[5]) * id;
+      geo[6] = (h[3] * h[7] - h[4] * h[6]) * id;
+      geo[7] = (h[1] * h[6] - h[0] * h[7]) * id;
+      geo[8] = (h[0] * h[4] - h[1] * h[3]) * id;
+      const double vol = fabs(det);
+      for (int k = 0; k < 3; ++k) {
+        const double *p = h + 3 * ((k + 1) % 3);
+        const double *q = h + 3 * ((k + 2) % 3);
+        const double cx = p[1] * q[2] - p[2] * q[1], cy = p[2] * q[0] - p[0] * q[2], cz = p[0] * q[1] - p[1] * q[0];
+        geo[9 + k] = a.r_list / (vol / sqrt(cx * cx + cy * cy + cz * cz));
+      }
+      if (c0 == 0) {
+        for (int k = 0; k < 9; ++k) a.ref_cell[9 * (int64_t)s + k] = h[k];
+        atomicAdd((unsigned long long *)&a.status[TS_STATUS_REBUILDS], 1ull);
+      }
+    }
+    __syncthreads();
+    const int li = c0 + wave;
+    if (li >= ns) continue;  // uniform over the wavefront; no block barrier follows before the loop top
+    const int64_t i = a0 + li;
+    const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
+                 h22 = h[8];
+    const double rx = lx[li], ry = ly[li], rz = lz[li];
+    int cnt = 0;
+    bool shift_bad = false;
+    for (int j0 = 0; j0 < ns; j0 += kWave) {
+      const int j = j0 + lane;
+      int c = 0;
+      uint32_t e1 = 0;
+      int lo0 = 0, hi0 = -1, lo1 = 0, hi1 = -1, lo2 = 0, hi2 = -1;
+      double drx = 0.0, dry = 0.0, drz = 0.0;
+      if (j < ns) {
+        drx = lx[j] - rx;
+        dry = ly[j] - ry;
+        drz = lz[j] - rz;
+        // images S with |ds_k + S_k| w_k < r_list along every direction (ds: fractional difference)
+        const double f0 = drx * geo[0] + dry * geo[3] + drz * geo[6];
+        const double f1 = drx * geo[1] + dry * geo[4] + drz * geo[7];
+        const double f2 = drx * geo[2] + dry * geo[5] + drz * geo[8];
+        lo0 = (int)ceil(-f0 - geo[9] - 1e-9);
+        hi0 = (int)floor(-f0 + geo[9] + 1e-9);
+        lo1 = (int)ceil(-f1 - geo[10] - 1e-9);
+        hi1 = (int)floor(-f1 + geo[10] + 1e-9);
+        lo2 = (int)ceil(-f2 - geo[11] - 1e-9);
+        hi2 = (int)floor(-f2 + geo[11] + 1e-9);
+        for (int S0 = lo0; S0 <= hi0; ++S0)
+          for (int S1 = lo1; S1 <= hi1; ++S1)
+            for (int S2 = lo2; S2 <= hi2; ++S2) {
+              if (j == li && S0 == 0 && S1 == 0 && S2 == 0) continue;
+              const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+              const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+              const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+              if (!(norm2(dx, dy, dz) < rl2)) continue;
+              if (a.half) {
+                const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
+                if (!(li < j || (li == j && fs > 0))) continue;
+              }
+              if (S0 < -TS_MAX_IMAGE_SHIFT || S0 > TS_MAX_IMAGE_SHIFT || S1 < -TS_MAX_IMAGE_SHIFT ||
+                  S1 > TS_MAX_IMAGE_SHIFT || S2 < -TS_MAX_IMAGE_SHIFT || S2 > TS_MAX_IMAGE_SHIFT) {
+                shift_bad = true;
+                continue;
+              }
+              if (c == 0) e1 = pack_entry(j, S0, S1, S2);
+              ++c;
+            }
+      }
+      // exclusive prefix of the per-lane counts across the wavefront
+      int pre, total;
+      const uint64_t multi = __ballot(c > 1);
+      if (multi == 0) {
+        const uint64_t one = __ballot(c == 1);
+        pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(one >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)one, 0));
+        total = __popcll(one);
+      } else {
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int t = __shfl_up(incl, o, kWave);
+          if (lane >= o) incl += t;
+        }
+        pre = incl - c;
+        total = __shfl(incl, kWave - 1, kWave);
+      }
+      int pos = cnt + pre;
+      if (c == 1) {
+        if (pos < a.max_nbr) a.nbr[(int64_t)pos * st + i] = e1;
+      } else if (c > 1) {
+        for (int S0 = lo0; S0 <= hi0; ++S0)
+          for (int S1 = lo1; S1 <= hi1; ++S1)
+            for (int S2 = lo2; S2 <= hi2; ++S2) {
+              if (j == li && S0 == 0 && S1 == 0 && S2 == 0) continue;
+              const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+              const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+              const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+              if (!(norm2(dx, dy, dz) < rl2)) continue;
+              if (a.half) {
+                const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
+                if (!(li < j || (li == j && fs > 0))) continue;
+              }
+              if (S0 < -TS_MAX_IMAGE_SHIFT || S0 > TS_MAX_IMAGE_SHIFT || S1 < -TS_MAX_IMAGE_SHIFT ||
+                  S1 > TS_MAX_IMAGE_SHIFT || S2 < -TS_MAX_IMAGE_SHIFT || S2 > TS_MAX_IMAGE_SHIFT)
+                continue;
+              if (pos < a.max_nbr) a.nbr[(int64_t)pos * st + i] = pack_entry(j, S0, S1, S2);
+              ++pos;
+            }
+      }
+      cnt += total;
+    }
+    if (lane == 0) {
+      a.n_nbr[i] = cnt < a.max_nbr ? cnt : a.max_nbr;
+      a.ref_pos[i] = rx;
+      a.ref_pos[st + i] = ry;
+      a.ref_pos[2 * st + i] = rz;
+      atomicMax((unsigned long long *)&a.status[TS_STATUS_MAX_NBR], (unsigned long long)cnt);
+      if (cnt > a.max_nbr) atomicMax((unsigned long long *)&a.status[TS_STATUS_OVERFLOW], 1ull);
+      if (!(isfinite(rx) && isfinite(ry) && isfinite(rz)))
+        atomicMax((unsigned long long *)&a.status[TS_STATUS_NONFINITE], 1ull);
+    }
+    if (__ballot(shift_bad) != 0 && lane == 0) atomicMax((unsigned long long *)&a.status[TS_STATUS_SHIFT], 1ull);
+  }
+}
+
+int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st) {
+  const int chunks = (int)ceil_div(max_atoms, kRebuildWaves);
+  const int64_t work = n_sys * chunks;
+  const unsigned grid = (unsigned)(work < 1024 ? work : 1024);
+  const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
+  hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, a, chunks);
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+template <int KIND, typename T, int TL>
+static void launch_step_k(int mode, const StepArgs &a, const PairTable &t, dim3 g, size_t shm, hipStream_t st) {
+  if (mode == kStepFirst)
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepFirst>), g, dim3(256), 0, st, a, t);
+  else if (mode == kStepMid)
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepMid>), g, dim3(256), shm, st, a, t);
+  else
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLast>), g, dim3(256), shm, st, a, t);
+}
+
+template <int KIND, typename T>
+static void launch_step_kt(int tl, int mode, const StepArgs &a, const PairTable &t, dim3 g, size_t shm,
+                           hipStream_t st) {
+  switch (tl) {
+    case 1: launch_step_k<KIND, T, 1>(mode, a, t, g, shm, st); break;
+    case 2: launch_step_k<KIND, T, 2>(mode, a, t, g, shm, st); break;
+    case 4: launch_step_k<KIND, T, 4>(mode, a, t, g, shm, st); break;
+    default: launch_step_k<KIND, T, 8>(mode, a, t, g, shm, st); break;
+  }
+}
+
+int launch_step(int mode, int tl, const StepArgs &a, const PairTable &t, int prec, int64_t n_sys, int64_t max_atoms,
+                hipStream_t st) {
+  const int apb = 256 / tl;
+  const dim3 g((unsigned)ceil_div(max_atoms, apb), (unsigned)n_sys);
+  const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
+  if (prec == TS_PAIR_F32) {
+    if (t.kind == TS_LJ) launch_step_kt<TS_LJ, float>(tl, mode, a, t, g, shm, st);
+    else if (t.kind == TS_MORSE) launch_step_kt<TS_MORSE, float>(tl, mode, a, t, g, shm, st);
+    else launch_step_kt<TS_SOFT_SPHERE, float>(tl, mode, a, t, g, shm, st);
+  } else {
+    if (t.kind == TS_LJ) launch_step_kt<TS_LJ, double>(tl, mode, a, t, g, shm, st);
+    else if (t.kind == TS_MORSE) launch_step_kt<TS_MORSE, double>(tl, mode, a, t, g, shm, st);
+    else launch_step_kt<TS_SOFT_SPHERE, double>(tl, mode, a, t, g, shm, st);
+  }
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+}  // namespace ts

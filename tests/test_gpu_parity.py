@@ -317,3 +317,61 @@ def test_rdf_and_vjp():
     api.ts_rdf_vjp(b, nl, n_bins, r_end, sig, r_max, dl, grad)
     grad_ref = oadj.rdf_loss_grad(w.pos, w.cell, w.sys_offsets, n_bins, r_end, sig, r_max, g_ref, g_ref * 1.01)
     assert np.abs(grad.T.cpu().numpy() - grad_ref).max() <= 1e-9 * np.abs(grad_ref).max()
+
+
+# ----------------------------------------------------------------------------- fused step loop
+
+
+def _run_nve(w, prec, steps, lanes, unfused, use_graph=True):
+    import os
+    api = _api()
+    os.environ["TS_NVE_UNFUSED"] = "1" if unfused else "0"
+    try:
+        b = _batch(w)
+        nl = api.build_neighbor_list(b, w.potential.cutoff, w.skin, bin_factor=2, lanes_per_atom=lanes)
+        pp = api.pair_params_from_spec(w.potential, prec)
+        F, _, _ = api.compute_forces(b, nl, pp, prec)
+        E = torch.zeros(w.n_systems, dtype=torch.float64, device="cuda")
+        W = torch.zeros((w.n_systems, 9), dtype=torch.float64, device="cuda")
+        nl.status.zero_()
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, steps, F, E, None, W, use_graph=use_graph)
+        torch.cuda.synchronize()
+        return b, nl, F, E, W
+    finally:
+        os.environ.pop("TS_NVE_UNFUSED", None)
+
+
+def test_fused_step_equals_multikernel_step():
+    w = argon_batch(3, seed=21, reps=(4, 4, 4))
+    ref = _run_nve(w, "f32", 40, 1, unfused=True)
+    one = _run_nve(w, "f32", 40, 1, unfused=False)
+    four = _run_nve(w, "f32", 40, 4, unfused=False)
+    # one lane per atom sums each row in the same order: bit-identical trajectory and lists
+    assert torch.equal(ref[0].pos, one[0].pos) and torch.equal(ref[0].vel, one[0].vel)
+    assert torch.equal(ref[2], one[2])
+    assert torch.equal(ref[1].n_nbr, one[1].n_nbr)
+    assert ref[1].read_status()[2] == one[1].read_status()[2]
+    # four lanes per atom change only the float64 summation order of each row
+    assert (ref[0].pos - four[0].pos).abs().max().item() <= 1e-10
+    assert np.allclose(ref[3].cpu().numpy(), four[3].cpu().numpy(), rtol=1e-9)
+    assert np.allclose(ref[4].cpu().numpy(), four[4].cpu().numpy(), rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.parametrize("lanes", [2, 8])
+def test_fused_lists_match_oracle_at_reference_positions(lanes):
+    # after steps with rebuilds inside the step kernel, each system's list is the oracle's pair set at the
+    # positions of that system's last rebuild
+    w = copper_uneven_batch(5, seed=22, min_sites=32, max_sites=400)
+    w.vel[:] = np.random.default_rng(0).normal(0, 0.2, w.vel.shape)
+    w.skin = 0.2
+    b, nl, F, E, W = _run_nve(w, "f32", 25, lanes, unfused=False)
+    assert nl.read_status()[2] > 5
+    ref = nl.ref_pos.T.cpu().numpy()
+    assert_same_pairs(b, nl, w.potential.cutoff + w.skin, pos=ref)
+    # and the final forces, energies and virials are the oracle's at the final positions
+    pos = b.positions()
+    E_ref, F_ref, W_ref = oforces.batch_efw(pos, w.cell, w.sys_offsets, w.species, w.potential)
+    A, se, sw = force_scales(pos, w.cell, w.sys_offsets, w.species, w.potential)
+    assert_forces_close(F.T.double().cpu().numpy(), F_ref, A, 1e-5)
+    assert np.all(np.abs(E.cpu().numpy() - E_ref) <= 1e-6 * se)
+    assert np.all(np.abs(W.cpu().numpy().reshape(-1, 3, 3) - W_ref).max(axis=(1, 2)) <= 1e-6 * sw)

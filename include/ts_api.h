@@ -195,15 +195,21 @@ typedef struct {
   double *scratch;    /* device [S][32] float64 working space */
 } ts_fire_state;
 
-/* Advance every unconverged system by up to n_iter FIRE iterations (n_iter >= 1), then evaluate
-   forces and the convergence test at the final configuration: on completion force/energy/virial
-   (each may be NULL; force is required) describe the final positions and converged[] is current.
+/* Advance every unconverged system by up to n_iter FIRE iterations, then evaluate forces and the
+   convergence test at the final configuration: on completion force/energy/virial (each may be
+   NULL; force is required) describe the final positions and converged[] is current.
+   persistent = 0: each iteration is a few launches over the whole batch (n_iter >= 1).
+   persistent = 1: one launch; workgroups take systems from a device work queue (largest first),
+   keep a system's positions in LDS and iterate it to convergence (n_iter = -1: until converged or
+   max_iter) before taking the next, so a converged system frees its workgroup at once (the
+   in-flight batching of the paper's Section 3, on the device).  Systems above 2048 atoms use the
+   per-iteration path.
    The caller initialises the state (vel = 0, dt = dt_start, alpha = alpha_start, n_pos = 0,
    converged = 0, n_iter = 0, deform = I, deform_vel = 0, ref_cell = cell).
    Errors: TS_E_INVALID, TS_E_UNSUPPORTED. */
 int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,
                  const ts_pair_params *pp, int64_t n_iter, void *force, double *energy, double *virial,
-                 ts_stream_t stream);
+                 int32_t persistent, ts_stream_t stream);
 
 /* Adjoint of velocity-Verlet sub-steps (differentiable simulation, paper Section 2).  With
    lr = adj_pos = dL/dr and lv = adj_vel = dL/dv (SoA float64), u = accel lv / m and J = dF/dr

@@ -120,7 +120,7 @@ SIGNATURES = {
     "ts_nve_step": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double, c_double,
                               c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "ts_fire_step": (c_int32, [POINTER(TsBatch), POINTER(TsFireState), POINTER(TsFireConfig), POINTER(TsNeighborList),
-                               POINTER(TsPairParams), c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+                               POINTER(TsPairParams), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "ts_pair_adjoint": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double,
                                   c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ts_rdf_smeared": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), c_int32, c_double, c_double, c_double,

@@ -260,11 +260,12 @@ def ts_nve_step(batch, nl, pp, dt, accel, n_steps, force, epot=None, ekin=None, 
                                                       1 if use_graph else 0, _stream(stream)))
 
 
-def ts_fire_step(batch, fs: FireState, cfg, nl, pp, n_iter, force, energy=None, virial=None, stream=None):
+def ts_fire_step(batch, fs: FireState, cfg, nl, pp, n_iter, force, energy=None, virial=None, persistent=False,
+                 stream=None):
     return N.check("ts_fire_step", N.lib().ts_fire_step(ctypes.byref(batch.struct()), ctypes.byref(fs.struct()),
                                                         ctypes.byref(cfg), ctypes.byref(nl.struct()),
                                                         ctypes.byref(pp), int(n_iter), _p(force), _p(energy),
-                                                        _p(virial), _stream(stream)))
+                                                        _p(virial), 1 if persistent else 0, _stream(stream)))
 
 
 def ts_pair_adjoint(batch, nl, pp, dt_drift, w_kick, accel, adj_pos, adj_vel, adj_params=None, stream=None):

@@ -4,25 +4,12 @@
 // unconverged systems, and one workgroup per system that reduces the FIRE scalars of its system
 // (max |F|, g.v, |v|^2, |g|^2 in a fixed order), takes the FIRE decision and updates the
 // system's atoms (and cell) -- no grid-wide synchronisation inside an iteration's update.
-#include "ts_forces.h"
-#include "ts_neighbor.h"
+#include "ts_fire.h"
+#include "ts_step.h"
 
 namespace ts {
 
-struct FireArgs {
-  int64_t stride;
-  const int64_t *offs;
-  double *pos, *vel;
-  const double *mass;
-  double *cell;
-  const void *force;
-  const double *virial;  // [S][9] (relax_cell)
-  double *dt, *alpha;
-  int32_t *n_pos, *converged;
-  int64_t *n_iter;
-  double *deform, *deform_vel, *ref_cell;
-  ts_fire_config cfg;
-};
+
 
 __device__ inline void inv3d(const double *h, double *inv) {
   const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
@@ -219,35 +206,17 @@ static void launch_fire_update(const FireArgs &fa, bool cell, int final_check, i
     hipLaunchKernelGGL((k_fire_update<T, false>), dim3((unsigned)n_sys), dim3(256), 0, st, fa, final_check);
 }
 
-}  // namespace ts
-
-extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,
-                            const ts_pair_params *pp, int64_t n_iter, void *force, double *energy, double *virial,
-                            ts_stream_t stream) {
-  int64_t max_atoms = 0;
-  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, true);
-  if (rc != TS_OK) return rc;
-  TS_CHECK_ARG(fs && cfg && force && n_iter >= 1);
-  TS_CHECK_ARG(fs->dt && fs->alpha && fs->n_pos && fs->converged && fs->n_iter && fs->scratch);
-  TS_CHECK_ARG(cfg->fmax > 0.0 && cfg->dt_start > 0.0 && cfg->dt_max > 0.0 && cfg->f_dec > 0.0 && cfg->f_inc > 0.0);
-  const bool cell = cfg->relax_cell != 0;
-  if (cell) {
-    TS_CHECK_ARG(fs->deform && fs->deform_vel && fs->ref_cell && cfg->cell_mass > 0.0);
-    for (int64_t s = 0; s < batch->n_systems; ++s)
-      TS_CHECK_ARG(batch->h_sys_offsets[s + 1] > batch->h_sys_offsets[s]);
-  }
-  hipStream_t st = ts::as_stream(stream);
-  const ts::PairTable tab = ts::make_table(pp);
-  double *vir = virial ? virial : fs->scratch;  // scratch holds [S][9] when the caller wants no virial
-  ts::FireArgs fa;
-  fa.stride = ts::stride_of(batch);
-  fa.offs = batch->sys_offsets;
-  fa.pos = batch->pos;
-  fa.vel = batch->vel;
-  fa.mass = batch->mass;
-  fa.cell = batch->cell;
+FireArgs make_fire_args(const ts_batch *b, const ts_fire_state *fs, const ts_fire_config *cfg, void *force,
+                        double *virial) {
+  FireArgs fa;
+  fa.stride = stride_of(b);
+  fa.offs = b->sys_offsets;
+  fa.pos = b->pos;
+  fa.vel = b->vel;
+  fa.mass = b->mass;
+  fa.cell = b->cell;
   fa.force = force;
-  fa.virial = vir;
+  fa.virial = virial;
   fa.dt = fs->dt;
   fa.alpha = fs->alpha;
   fa.n_pos = fs->n_pos;
@@ -257,6 +226,33 @@ extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_f
   fa.deform_vel = fs->deform_vel;
   fa.ref_cell = fs->ref_cell;
   fa.cfg = *cfg;
+  return fa;
+}
+
+}  // namespace ts
+
+extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,
+                            const ts_pair_params *pp, int64_t n_iter, void *force, double *energy, double *virial,
+                            int32_t persistent, ts_stream_t stream) {
+  int64_t max_atoms = 0;
+  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, true);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(fs && cfg && force && (n_iter >= 1 || (persistent && n_iter == -1)));
+  TS_CHECK_ARG(fs->dt && fs->alpha && fs->n_pos && fs->converged && fs->n_iter && fs->scratch);
+  TS_CHECK_ARG(cfg->fmax > 0.0 && cfg->dt_start > 0.0 && cfg->dt_max > 0.0 && cfg->f_dec > 0.0 && cfg->f_inc > 0.0);
+  const bool cell = cfg->relax_cell != 0;
+  if (cell) {
+    TS_CHECK_ARG(fs->deform && fs->deform_vel && fs->ref_cell && cfg->cell_mass > 0.0);
+    for (int64_t s = 0; s < batch->n_systems; ++s)
+      TS_CHECK_ARG(batch->h_sys_offsets[s + 1] > batch->h_sys_offsets[s]);
+  }
+  hipStream_t st = ts::as_stream(stream);
+  if (persistent && max_atoms <= ts::kLdsMaxAtoms)
+    return ts::fire_persistent(batch, fs, cfg, nl, pp, n_iter, force, energy, virial, max_atoms, st);
+  TS_CHECK_ARG(n_iter >= 1);
+  const ts::PairTable tab = ts::make_table(pp);
+  double *vir = virial ? virial : fs->scratch;  // scratch holds [S][9] when the caller wants no virial
+  const ts::FireArgs fa = ts::make_fire_args(batch, fs, cfg, force, vir);
   for (int64_t it = 0; it <= n_iter; ++it) {
     const bool last = it == n_iter;
     rc = ts::nl_update(batch, nl, 0, max_atoms, st);

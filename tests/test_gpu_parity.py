@@ -214,8 +214,8 @@ def _fire_cfg_dict(**kw):
     return d
 
 
-@pytest.mark.parametrize("relax_cell", [False, True])
-def test_fire_iterations_match_oracle(relax_cell):
+@pytest.mark.parametrize("relax_cell,persistent", [(False, False), (True, False), (False, True), (True, True)])
+def test_fire_iterations_match_oracle(relax_cell, persistent):
     api = _api()
     w = copper_uneven_batch(4, seed=11, min_sites=32, max_sites=120)
     pot = w.potential
@@ -227,7 +227,7 @@ def test_fire_iterations_match_oracle(relax_cell):
     fs = api.FireState(b, cfg)
     F = api.force_buffer(b, "f64")
     n_it = 12
-    api.ts_fire_step(b, fs, cfg, nl, pp, n_it, F)
+    api.ts_fire_step(b, fs, cfg, nl, pp, n_it, F, persistent=persistent)
     ocfg = ofire.FireConfig(**cfgd)
     for s in range(w.n_systems):
         sl = w.system(s)
@@ -241,7 +241,8 @@ def test_fire_iterations_match_oracle(relax_cell):
         assert abs(fs.dt[s].item() - st.dt) <= 1e-12 * st.dt
 
 
-def test_fire_relaxation_certified_by_oracle():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_fire_relaxation_certified_by_oracle(persistent):
     api = _api()
     w = copper_uneven_batch(5, seed=12, min_sites=32, max_sites=200)
     pot = w.potential
@@ -252,10 +253,13 @@ def test_fire_relaxation_certified_by_oracle():
     cfg = api.fire_config(**cfgd)
     fs = api.FireState(b, cfg)
     F = api.force_buffer(b, "f32")
-    for _ in range(40):
-        api.ts_fire_step(b, fs, cfg, nl, pp, 100, F)
-        if fs.converged.all().item():
-            break
+    if persistent:
+        api.ts_fire_step(b, fs, cfg, nl, pp, 4000, F, persistent=True)
+    else:
+        for _ in range(40):
+            api.ts_fire_step(b, fs, cfg, nl, pp, 100, F)
+            if fs.converged.all().item():
+                break
     assert fs.converged.all().item()
     pos, cell = b.positions(), b.cells()
     for s in range(w.n_systems):

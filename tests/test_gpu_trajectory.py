@@ -1,0 +1,116 @@
+"""GPU parity of the checkpointed trajectory gradient (RDF loss after velocity-Verlet NVE) against
+the FP64 oracle's reverse pass and against central finite differences."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from workloads import PotentialSpec, argon_batch
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N_STEPS, CKPT = 20, 8
+RDF = dict(n_bins=200, r_end=10.0, sigma=0.05)
+
+
+def _workload():
+    # two 108-atom argon systems: cells narrower than twice the RDF range (several images in range)
+    return argon_batch(2, reps=(3, 3, 3), seed=31, n_steps=N_STEPS)
+
+
+def _oracle(w, eps, sig, target):
+    pot = PotentialSpec("lj", np.array([[[eps, sig, 0.0]]]), w.potential.cutoff, w.potential.shift_energy)
+    traj, _ = oadj.trajectory_positions(w.pos, w.vel, w.mass, w.cell, w.sys_offsets, w.species, pot, w.dt, N_STEPS,
+                                        w.accel)
+    r_max = RDF["r_end"] + 6 * RDF["sigma"]
+    g = oadj.batch_rdf(traj[-1], w.cell, w.sys_offsets, RDF["n_bins"], RDF["r_end"], RDF["sigma"], r_max)
+    if target is None:
+        return g
+    loss = oadj.rdf_loss(g, target)
+    lr_T = oadj.rdf_loss_grad(traj[-1], w.cell, w.sys_offsets, RDF["n_bins"], RDF["r_end"], RDF["sigma"], r_max, g,
+                              target)
+    lr0, _, tb = oadj.reverse_nve(traj, w.mass, w.cell, w.sys_offsets, w.species, pot, w.dt, w.accel, lr_T,
+                                  np.zeros_like(lr_T))
+    return loss, lr0, tb[0, 0, 0], tb[0, 0, 1]
+
+
+@pytest.fixture(scope="module")
+def problem():
+    assert torch.cuda.is_available()
+    w = _workload()
+    eps, sig = float(w.potential.params[0, 0, 0]), float(w.potential.params[0, 0, 1])
+    target = _oracle(w, eps * 1.05, sig * 1.05, None)
+    ref = _oracle(w, eps, sig, target)
+    return w, eps, sig, target, ref
+
+
+def _engine(w, prec):
+    from paper_2508_06628_amd.trajectory import RdfSpec, TrajectoryRDF
+    eng = TrajectoryRDF(w, N_STEPS, CKPT, prec=prec, rdf=RdfSpec(**RDF))
+    return eng
+
+
+def test_gradient_fp64_matches_oracle_reverse_pass(problem):
+    w, eps, sig, target, (loss_ref, lr0_ref, de_ref, ds_ref) = problem
+    eng = _engine(w, "f64")
+    eng.set_target(torch.tensor(target, device="cuda"))
+    pos0 = eng.batch.pos.clone()
+    loss = eng.forward(eps, sig, pos0).item()
+    de, ds, lr0 = eng.backward()
+    assert abs(loss - loss_ref) <= 1e-9 * abs(loss_ref)
+    assert abs(de - de_ref) <= 1e-8 * abs(de_ref)
+    assert abs(ds - ds_ref) <= 1e-8 * abs(ds_ref)
+    g = lr0.T.cpu().numpy()
+    assert np.abs(g - lr0_ref).max() <= 1e-8 * np.abs(lr0_ref).max()
+
+
+def test_gradient_fp32_within_1e3_of_oracle(problem):
+    w, eps, sig, target, (loss_ref, lr0_ref, de_ref, ds_ref) = problem
+    eng = _engine(w, "f32")
+    eng.set_target(torch.tensor(target, device="cuda"))
+    pos0 = eng.batch.pos.clone()
+    eng.forward(eps, sig, pos0)
+    de, ds, lr0 = eng.backward()
+    assert abs(de - de_ref) <= 1e-3 * abs(de_ref)
+    assert abs(ds - ds_ref) <= 1e-3 * abs(ds_ref)
+    assert np.abs(lr0.T.cpu().numpy() - lr0_ref).max() <= 1e-3 * np.abs(lr0_ref).max()
+
+
+def test_gradient_matches_central_differences(problem):
+    w, eps, sig, target, _ = problem
+    eng = _engine(w, "f64")
+    eng.set_target(torch.tensor(target, device="cuda"))
+    pos0 = eng.batch.pos.clone()
+    eng.forward(eps, sig, pos0)
+    de, ds, lr0 = eng.backward()
+
+    def L(e, s, p):
+        return eng.forward(e, s, p).item()
+
+    h = 1e-4
+    fd_e = (L(eps * (1 + h), sig, pos0) - L(eps * (1 - h), sig, pos0)) / (2 * h * eps)
+    fd_s = (L(eps, sig * (1 + h), pos0) - L(eps, sig * (1 - h), pos0)) / (2 * h * sig)
+    assert abs(fd_e - de) <= 1e-6 * abs(de)
+    assert abs(fd_s - ds) <= 1e-6 * abs(ds)
+    rng = np.random.default_rng(4)
+    u = rng.normal(size=pos0.shape)
+    u /= np.linalg.norm(u)
+    ut = torch.tensor(u, device="cuda")
+    hp = 1e-4 * sig
+    fd_p = (L(eps, sig, pos0 + hp * ut) - L(eps, sig, pos0 - hp * ut)) / (2 * hp)
+    assert abs(fd_p - float((lr0 * ut).sum())) <= 1e-6 * max(abs(fd_p), 1e-3 * float(lr0.abs().max()))
+
+
+def test_autograd_function_routes_through_the_engine(problem):
+    from paper_2508_06628_amd.trajectory import TrajectoryLoss
+    w, eps, sig, target, (loss_ref, lr0_ref, de_ref, ds_ref) = problem
+    eng = _engine(w, "f64")
+    eng.set_target(torch.tensor(target, device="cuda"))
+    e_t = torch.tensor(eps, dtype=torch.float64, device="cuda", requires_grad=True)
+    s_t = torch.tensor(sig, dtype=torch.float64, device="cuda", requires_grad=True)
+    p_t = eng.batch.pos.clone().requires_grad_(True)
+    loss = TrajectoryLoss.apply(e_t, s_t, p_t, eng)
+    loss.backward()
+    assert abs(e_t.grad.item() - de_ref) <= 1e-8 * abs(de_ref)
+    assert abs(s_t.grad.item() - ds_ref) <= 1e-8 * abs(ds_ref)
+    assert np.abs(p_t.grad.T.cpu().numpy() - lr0_ref).max() <= 1e-8 * np.abs(lr0_ref).max()

@@ -29,11 +29,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor):
+def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes):
     pot = w.potential
     b = api.Batch.from_workload(w)
     nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
     pp = api.pair_params_from_spec(pot, w.pair_prec)
+    tune = None
+    if lanes == 0:
+        from paper_2508_06628_amd.autotune import tune_nve
+        tune = tune_nve(b, nl, pp, w.dt, w.accel)
+        log(f"autotune: {tune}")
+    else:
+        nl.lanes_per_atom = lanes
     F = api.force_buffer(b, w.pair_prec)
     api.ts_pair_forces(b, nl, pp, F)
     chunk = max(1, min(chunk, steps))
@@ -61,7 +68,8 @@ def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor):
     if st[1] or st[3] or st[4]:
         raise RuntimeError(f"neighbor list status after the timed run: {st.tolist()}")
     return dict(ms=ms, wall_s=wall, warmup_steps=w_runs * chunk + rest, rebuilds=int(st[2]),
-                max_nbr=int(st[0]), capacity=nl.max_nbr, batch=b, nl=nl, pp=pp, F=F)
+                max_nbr=int(st[0]), capacity=nl.max_nbr, batch=b, nl=nl, pp=pp, F=F, lanes=nl.lanes_per_atom,
+                tune=tune)
 
 
 def force_kernel_roofline(api, torch, r, reps=200):
@@ -157,6 +165,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=15)
     ap.add_argument("--chunk", type=int, default=100)
     ap.add_argument("--bin-factor", type=int, default=2)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per atom in the step kernel (0: autotune)")
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=500)
     ap.add_argument("--no-plain", action="store_true")
@@ -175,7 +184,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     w = argon_batch(64, seed=1, n_steps=args.steps)
     log(f"workload {w.name}: {w.n_systems} systems, {w.n_atoms} atoms")
-    r = batched_nve(api, torch, w, args.steps, args.warmup, args.chunk, args.bin_factor)
+    r = batched_nve(api, torch, w, args.steps, args.warmup, args.chunk, args.bin_factor, args.lanes)
     ms_per_step = r["ms"] / args.steps
     value = w.n_atoms * args.steps / (r["ms"] * 1e-3)
     log(f"batched NVE: {ms_per_step * 1e3:.2f} us/step, {value:.4g} atom-steps/s, rebuilds {r['rebuilds']}")
@@ -197,6 +206,7 @@ def main():
         "config": {"workload": "argon_lj_nve_64x864", "n_systems": w.n_systems, "atoms_per_system": 864,
                    "n_atoms": w.n_atoms, "dt_fs": w.dt, "skin_A": w.skin, "cutoff_A": w.potential.cutoff,
                    "pair_prec": w.pair_prec, "graph_chunk_steps": args.chunk, "bin_factor": args.bin_factor,
+                   "lanes_per_atom": r["lanes"],
                    "list_capacity": r["capacity"], "max_list_len": r["max_nbr"], "system_rebuilds": r["rebuilds"],
                    "wall_s": round(r["wall_s"], 4)},
         "roofline": roof,

@@ -1,0 +1,103 @@
+"""Launch-shape autotuner for the batched NVE step loop.
+
+The fused step kernel spreads each atom's neighbor row over ``lanes_per_atom`` lanes of a
+wavefront (1, 2, 4 or 8).  The best value depends on the row length and on how many atoms the
+batch has (few atoms need more lanes per atom to fill 256 CUs).  ``tune_nve`` times a short graph
+replay of the real workload for every candidate on a scratch copy of the state and returns the
+fastest; results are cached on disk per (device architecture, potential, precision, size bucket)
+so later runs skip the sweep.  Only timing is done here: every candidate runs the same kernels
+through the C ABI and computes the same trajectory up to float64 summation order.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Optional
+
+import torch
+
+from . import api
+
+LANE_CHOICES = (1, 2, 4, 8)
+
+
+def cache_path() -> str:
+    root = os.environ.get("TS_AUTOTUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "ts_mi355x")
+    return os.path.join(root, "autotune.json")
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: dict) -> None:
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass  # a read-only home only disables caching
+
+
+def size_bucket(batch: api.Batch, nl: api.NeighborList) -> str:
+    """Bucket of (atoms per batch, largest system, mean row length) on a log2 scale."""
+    n = max(batch.n_atoms, 1)
+    mean_row = float(nl.n_nbr.float().mean().item()) if batch.n_atoms else 0.0
+    return f"n{int(math.log2(n))}_m{int(math.log2(max(batch.max_system_atoms, 1)))}_r{int(math.log2(mean_row + 1))}"
+
+
+def key(batch, nl, pp) -> str:
+    arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
+    return f"{arch}/kind{pp.kind}/prec{pp.prec}/{size_bucket(batch, nl)}"
+
+
+def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float, steps: int = 50,
+             reps: int = 3, use_cache: bool = True, choices=LANE_CHOICES) -> dict:
+    """Pick lanes_per_atom for ``ts_nve_step`` on this workload.  Returns
+    {"lanes_per_atom": L, "us_per_step": {L: t, ...}, "cached": bool} and sets it on ``nl``."""
+    k = key(batch, nl, pp)
+    cache = _load() if use_cache else {}
+    if k in cache:
+        nl.lanes_per_atom = int(cache[k]["lanes_per_atom"])
+        return dict(cache[k], cached=True)
+    prec = "f32" if pp.prec == 0 else "f64"
+    timings = {}
+    for lanes in choices:
+        b = batch.clone()
+        trial = api.NeighborList(b, nl.cutoff, nl.skin, nl.max_nbr, nl.bin_factor, nl.half, lanes)
+        api.ts_neighbor_build(b, trial, force=True)
+        F = api.force_buffer(b, prec)
+        api.ts_pair_forces(b, trial, pp, F)
+        api.ts_nve_step(b, trial, pp, dt, accel, steps, F, use_graph=True)  # instantiate and warm up
+        torch.cuda.synchronize()
+        best = math.inf
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            api.ts_nve_step(b, trial, pp, dt, accel, steps, F, use_graph=True)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e3 / steps)
+        timings[lanes] = round(best, 3)
+        del trial, b, F
+    api.ts_release_graphs()
+    lanes = min(timings, key=timings.get)
+    entry = {"lanes_per_atom": int(lanes), "us_per_step": {str(k2): v for k2, v in timings.items()}}
+    if use_cache:
+        cache[k] = entry
+        _store(cache)
+    nl.lanes_per_atom = int(lanes)
+    return dict(entry, cached=False)
+
+
+def tuned_lanes(batch, nl, pp) -> Optional[int]:
+    e = _load().get(key(batch, nl, pp))
+    return None if e is None else int(e["lanes_per_atom"])

@@ -100,8 +100,9 @@ typedef struct {
   double params[TS_MAX_SPECIES][TS_MAX_SPECIES][3];
 } ts_pair_params;
 
-/* Neighbor list: padded per-atom rows.  Entry k of atom i is nbr[k * stride + i] for
-   k < n_nbr[i] <= max_nbr, packed as  j_local << 15 | (S0+16) << 10 | (S1+16) << 5 | (S2+16)
+/* Neighbor list: padded per-atom rows in blocks of 8 entries.  Entry k of atom i is
+   nbr[((k / 8) * stride + i) * 8 + k % 8] for k < n_nbr[i] <= max_nbr (so the 8 entries of a block
+   of one atom are contiguous), packed as  j_local << 15 | (S0+16) << 10 | (S1+16) << 5 | (S2+16)
    with j_local = j - sys_offsets[system of i] (so each system may hold up to 2^17 atoms).
    Rows are sorted by the unsigned entry value, i.e. by (j_local, S0, S1, S2): every builder
    produces the same row for the same pair set. 
@@ -119,7 +120,7 @@ typedef struct {
   int32_t bin_factor;  /* cell-list bins per list radius along each direction (1..4) */
   int32_t lanes_per_atom; /* lanes of a wavefront sharing one atom's row in the fused step
                              kernels: 1, 2, 4 or 8 (0 = 4) */
-  int32_t *nbr;        /* device [max_nbr][stride] */
+  int32_t *nbr;        /* device [ceil(max_nbr / 8)][stride][8] */
   int32_t *n_nbr;      /* device [N] */
   double *ref_pos;     /* device SoA [3][stride]: positions at the last build of each system */
   double *ref_cell;    /* device [S][9]: cell at the last build */

@@ -116,7 +116,7 @@ def pair_params_from_spec(spec, prec: str = "f32") -> N.TsPairParams:
 
 
 class NeighborList:
-    """Padded neighbor list of a batch (rows [max_nbr][N] of packed (j, S) entries)."""
+    """Padded neighbor list of a batch (rows of packed (j, S) entries, blocks of 8 per atom)."""
 
     def __init__(self, batch: Batch, cutoff: float, skin: float, max_nbr: int, bin_factor: int = 1, half: bool = False,
                  lanes_per_atom: int = 0):
@@ -129,7 +129,8 @@ class NeighborList:
         dev = batch.device
         stride = batch.pos.shape[1]
         self.max_nbr = max_nbr
-        self.nbr = torch.zeros((max_nbr, stride), dtype=torch.int32, device=dev)
+        # entry k of atom i lives at [k // 8, i, k % 8]
+        self.nbr = torch.zeros(((max_nbr + 7) // 8, stride, 8), dtype=torch.int32, device=dev)
         self.n_nbr = torch.zeros(batch.n_atoms, dtype=torch.int32, device=dev)
         self.ref_pos = torch.zeros((3, stride), dtype=torch.float64, device=dev)
         self.ref_cell = torch.zeros((batch.n_systems, 9), dtype=torch.float64, device=dev)
@@ -166,7 +167,7 @@ class NeighborList:
             sel = np.nonzero(n > k)[0]
             if sel.size == 0:
                 break
-            e = nbr[k, sel]
+            e = nbr[k // 8, sel, k % 8]
             rows.append((sel, (e >> 15).astype(np.int64), ((e >> 10) & 31).astype(np.int64) - 16,
                          ((e >> 5) & 31).astype(np.int64) - 16, (e & 31).astype(np.int64) - 16))
         if not rows:

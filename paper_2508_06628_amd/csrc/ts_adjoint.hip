@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_pair_vjp(AdjArgs a, PairTable tab) {
     double jx = 0.0, jy = 0.0, jz = 0.0;
     const PairCoef pc0 = tab.c[0];
     for (int k = 0; k < nn; ++k) {
-      const uint32_t ent = a.nbr[(int64_t)k * st + i];
+      const uint32_t ent = a.nbr[row_index(k, i, st)];
       const int64_t j = a0 + entry_j(ent);
       const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
       const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h[0], h[3], h[6]);
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(256) k_rdf_hist(RdfArgs a, double *g) {
     const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
     const double span = 10.0 * a.sigma;
     for (int k = 0; k < nn; ++k) {
-      const uint32_t ent = a.nbr[(int64_t)k * st + i];
+      const uint32_t ent = a.nbr[row_index(k, i, st)];
       const int64_t j = a0 + entry_j(ent);
       const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
       const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h[0], h[3], h[6]);
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(256) k_rdf_vjp(RdfArgs a, const double *dl_dg,
   const double span = 10.0 * a.sigma;
   double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int k = 0; k < nn; ++k) {
-    const uint32_t ent = a.nbr[(int64_t)k * st + i];
+    const uint32_t ent = a.nbr[row_index(k, i, st)];
     const int64_t j = a0 + entry_j(ent);
     const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
     const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h[0], h[3], h[6]);

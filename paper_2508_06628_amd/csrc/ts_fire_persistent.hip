@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
             }
             int pos = cnt + pre;
             if (c == 1) {
-              if (pos < a.max_nbr) a.nbr[(int64_t)pos * st + i] = e1;
+              if (pos < a.max_nbr) a.nbr[row_index(pos, i, st)] = e1;
             } else if (c > 1) {
               for (int S0 = lo0; S0 <= hi0; ++S0)
                 for (int S1 = lo1; S1 <= hi1; ++S1)
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
                     const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
                     const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
                     if (!(norm2(dx, dy, dz) < rl2)) continue;
-                    if (pos < a.max_nbr) a.nbr[(int64_t)pos * st + i] = pack_entry(j, S0, S1, S2);
+                    if (pos < a.max_nbr) a.nbr[row_index(pos, i, st)] = pack_entry(j, S0, S1, S2);
                     ++pos;
                   }
             }
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
           const int si = single ? 0 : a.species[i];
           const int nn = a.n_nbr[i];
           for (int k = gl; k < nn; k += tl) {
-            const uint32_t ent = a.nbr[(int64_t)k * st + i];
+            const uint32_t ent = a.nbr[row_index(k, i, st)];
             const int j = entry_j(ent);
             const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
             const double dx = shift_comp(lx[j] - rx, S0, S1, S2, h00, h10, h20);

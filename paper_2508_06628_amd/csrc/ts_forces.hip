@@ -7,6 +7,7 @@
 // float64.  Per-system energy and virial are reduced across the wavefront and added with one
 // float64 atomic per wavefront (lanes of a wavefront almost always share a system).
 #include "ts_forces.h"
+#include "ts_step.h"
 
 namespace ts {
 
@@ -33,7 +34,7 @@ __global__ void __launch_bounds__(256) k_pair_forces(ForceArgs a, PairTable tab)
     const double cut2 = tab.cut2;
     const PairCoef pc0 = tab.c[0];
     for (int k = 0; k < nn; ++k) {
-      const uint32_t ent = a.nbr[(int64_t)k * st + ii];
+      const uint32_t ent = a.nbr[row_index(k, ii, st)];
       const int64_t j = a0 + entry_j(ent);
       const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
       const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h00, h10, h20);
@@ -167,6 +168,29 @@ extern "C" int ts_pair_forces(const ts_batch *batch, const ts_neighbor_list *nl,
   if (rc != TS_OK) return rc;
   TS_CHECK_ARG(force != nullptr);
   const ts::PairTable t = ts::make_table(pp);
+  if (max_atoms <= ts::kLdsMaxAtoms && batch->n_atoms > 0) {
+    // systems that fit in LDS: the workgroup-per-system kernel the step loop uses, forces only
+    hipStream_t st = ts::as_stream(stream);
+    if (energy && (rc = ts::fill_async<double>(energy, batch->n_systems, 0.0, st)) != TS_OK) return rc;
+    if (virial && (rc = ts::fill_async<double>(virial, 9 * batch->n_systems, 0.0, st)) != TS_OK) return rc;
+    ts::StepArgs s;
+    std::memset(&s, 0, sizeof(s));
+    s.offs = batch->sys_offsets;
+    s.pos_in = batch->pos;
+    s.st_in = ts::stride_of(batch);
+    s.st_vel = ts::stride_of(batch);
+    s.species = batch->species;
+    s.cell = batch->cell;
+    s.force = force;
+    s.nbr = reinterpret_cast<uint32_t *>(nl->nbr);
+    s.n_nbr = nl->n_nbr;
+    s.max_nbr = nl->max_nbr;
+    s.epot = energy;
+    s.virial = virial;
+    const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : 4;
+    const int mode = (energy || virial) ? ts::kStepForceEV : ts::kStepForce;
+    return ts::launch_step(mode, tl, s, t, pp->prec, batch->n_systems, max_atoms, st);
+  }
   const ts::ForceArgs a = ts::make_force_args(batch, nl, force, energy, virial, nullptr);
   return ts::launch_forces(a, batch->n_systems, t, pp->prec, energy != nullptr || virial != nullptr,
                            ts::as_stream(stream));

@@ -57,6 +57,14 @@ __device__ inline int entry_s0(uint32_t e) { return (int)((e >> 10) & 31u) - 16;
 __device__ inline int entry_s1(uint32_t e) { return (int)((e >> 5) & 31u) - 16; }
 __device__ inline int entry_s2(uint32_t e) { return (int)(e & 31u) - 16; }
 
+// Row layout: entries come in blocks of kRowBlock per atom, block b of atom i at
+// nbr[(b * stride + i) * kRowBlock ...] -- the kRowBlock lanes that share an atom read one
+// contiguous 32-byte segment, and a wavefront writing one row writes contiguous segments.
+constexpr int kRowBlock = 8;
+__host__ __device__ inline int64_t row_index(int k, int64_t i, int64_t st) {
+  return ((int64_t)(k >> 3) * st + i) * kRowBlock + (k & (kRowBlock - 1));
+}
+
 // Pair vector component d_c = (r_j,c - r_i,c) + S @ cell (column c), written with explicit fused
 // multiply-adds so that every kernel evaluates it, and |d|^2, with the same rounding.
 __device__ inline double shift_comp(double dr, double S0, double S1, double S2, double h0c, double h1c, double h2c) {
@@ -85,6 +93,33 @@ struct PairTable {
 
 PairTable make_table(const ts_pair_params *pp);
 
+// Visit the row entries k = lane, lane + TL, lane + 2 TL, ... (k < nn) of atom i in increasing k,
+// with the loads of the next U entries in flight while the current U are processed (the entry
+// load heads a dependent chain, so issuing it early hides most of its latency).  The visiting
+// order is the plain loop's, so sums over the row round identically.
+template <int TL, typename F>
+__device__ inline void for_row(const uint32_t *__restrict__ nbr, int64_t st, int64_t i, int nn, int lane, F &&f) {
+  constexpr int U = 4;
+  uint32_t cur[U], nxt[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int kk = lane + u * TL;
+    cur[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
+  }
+  for (int k = lane; k < nn; k += U * TL) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = k + (U + u) * TL;
+      nxt[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k + u * TL < nn) f(cur[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+  }
+}
+
 // Copy the species-pair table into LDS using static indices only: indexing a by-value kernel
 // argument with a run-time index makes the compiler keep a private (scratch) copy per lane.
 // Must be reached by every thread of the workgroup.
@@ -102,7 +137,7 @@ __device__ inline T pair_g(const PairCoef &pc, T r2t, double r2, T *phi, bool wa
 
 template <>
 __device__ inline float pair_g<TS_LJ, float>(const PairCoef &pc, float r2t, double, float *phi, bool want_phi) {
-  const float ir2 = 1.0f / r2t;
+  const float ir2 = __builtin_amdgcn_rcpf(r2t);  // hardware reciprocal, 1 ulp
   const float ir6 = ir2 * ir2 * ir2;
   const float a = (float)pc.a, b = (float)pc.b;
   if (want_phi) *phi = ir6 * (a * ir6 - b) - (float)pc.shift;

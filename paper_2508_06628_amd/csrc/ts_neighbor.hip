@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
             shift_bad = true;
             continue;
           }
-          if (cnt < max_nbr) nbr[(int64_t)cnt * stride + i] = pack_entry((int)(j - a0), S0, S1, S2);
+          if (cnt < max_nbr) nbr[row_index(cnt, i, stride)] = pack_entry((int)(j - a0), S0, S1, S2);
           ++cnt;
         }
       }
@@ -328,13 +328,13 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
   // canonical row order: ascending packed entry = lexicographic (j, S0, S1, S2)
   const int nw = cnt < max_nbr ? cnt : max_nbr;
   for (int a = 1; a < nw; ++a) {
-    const uint32_t key = nbr[(int64_t)a * stride + i];
+    const uint32_t key = nbr[row_index(a, i, stride)];
     int q = a - 1;
-    while (q >= 0 && nbr[(int64_t)q * stride + i] > key) {
-      nbr[(int64_t)(q + 1) * stride + i] = nbr[(int64_t)q * stride + i];
+    while (q >= 0 && nbr[row_index(q, i, stride)] > key) {
+      nbr[row_index(q + 1, i, stride)] = nbr[row_index(q, i, stride)];
       --q;
     }
-    nbr[(int64_t)(q + 1) * stride + i] = key;
+    nbr[row_index(q + 1, i, stride)] = key;
   }
   n_nbr[i] = nw;
   atomicMax((unsigned long long *)&status[TS_STATUS_MAX_NBR], (unsigned long long)cnt);

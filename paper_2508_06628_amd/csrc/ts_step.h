@@ -8,6 +8,8 @@ namespace ts {
 constexpr int kStepFirst = 0;  // first half kick and drift (forces given)
 constexpr int kStepMid = 1;    // forces, two half kicks, drift, validity test
 constexpr int kStepLast = 2;   // forces (+ energy, virial), last half kick
+constexpr int kStepForce = 3;  // forces only (ts_pair_forces)
+constexpr int kStepForceEV = 4;  // forces, energy and virial (ts_pair_forces)
 constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)
 
 struct StepArgs {

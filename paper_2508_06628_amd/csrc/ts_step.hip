@@ -27,7 +27,6 @@ __device__ inline void flag_system(const StepArgs &a, int s) {
 template <int KIND, typename T, int TL, int MODE>
 __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   extern __shared__ double lds[];
-  __shared__ double geo[12];  // cell^-1 (9), reach (3)
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   constexpr int APB = 256 / TL;
   const int s = blockIdx.y;
@@ -73,33 +72,43 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                h22 = h[8];
   const double rx = own ? lx[li] : 0.0, ry = own ? ly[li] : 0.0, rz = own ? lz[li] : 0.0;
-  const uint32_t *nbr = a.nbr;
+  const uint32_t *__restrict__ nbr = a.nbr;
   const int64_t st = a.st_vel;  // list, reference positions, velocities and forces share the batch stride
   const int nn = own ? a.n_nbr[i] : 0;
+  const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0 && h00 > 0.0 &&
+                    h11 > 0.0 && h22 > 0.0;
 
   // 3. pair forces of this block's atoms, TL lanes per atom
-  constexpr bool EV = MODE == kStepLast;
+  constexpr bool EV = MODE == kStepLast || MODE == kStepForceEV;
+  constexpr bool FORCE_ONLY = MODE == kStepForce || MODE == kStepForceEV;
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
   double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
   if (own) {
     const bool single = tab.n_species == 1 || a.species == nullptr;
     const int si = single ? 0 : a.species[i];
     const double cut2 = tab.cut2;
-    for (int k = lane; k < nn; k += TL) {
-      const uint32_t ent = nbr[(int64_t)k * st + i];
+    const int32_t *__restrict__ species = a.species;
+    auto pair = [&](uint32_t ent, const PairCoef &pc, bool check_species) {
       const int j = entry_j(ent);
       const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
-      const double dx = shift_comp(lx[j] - rx, S0, S1, S2, h00, h10, h20);
-      const double dy = shift_comp(ly[j] - ry, S0, S1, S2, h01, h11, h21);
-      const double dz = shift_comp(lz[j] - rz, S0, S1, S2, h02, h12, h22);
+      double dx, dy, dz;
+      if (diag) {
+        // off-diagonal products are exact zeros: the same value as the general form below
+        dx = (lx[j] - rx) + S0 * h00;
+        dy = (ly[j] - ry) + S1 * h11;
+        dz = (lz[j] - rz) + S2 * h22;
+      } else {
+        dx = shift_comp(lx[j] - rx, S0, S1, S2, h00, h10, h20);
+        dy = shift_comp(ly[j] - ry, S0, S1, S2, h01, h11, h21);
+        dz = shift_comp(lz[j] - rz, S0, S1, S2, h02, h12, h22);
+      }
       const double r2 = norm2(dx, dy, dz);
-      if (!(r2 < cut2)) continue;
-      // coefficients are read from LDS in both cases (a local copy would live in scratch)
-      const PairCoef &pc = ltab[single ? 0 : si * TS_MAX_SPECIES + a.species[a0 + j]];
-      if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
+      if (!(r2 < cut2)) return;
+      const PairCoef &c = check_species ? ltab[si * TS_MAX_SPECIES + species[a0 + j]] : pc;
+      if (KIND == TS_SOFT_SPHERE && !(r2 < c.sig2)) return;
       const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
       T phi = (T)0;
-      const T g = pair_g<KIND, T>(pc, (T)r2, r2, &phi, EV);
+      const T g = pair_g<KIND, T>(c, (T)r2, r2, &phi, EV);
       const T gx = g * tx, gy = g * ty, gz = g * tz;
       fx += (double)gx;
       fy += (double)gy;
@@ -113,6 +122,12 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
         w4 += (double)(gx * tz);
         w5 += (double)(gy * tz);
       }
+    };
+    if (single) {
+      const PairCoef pc0 = ltab[0];  // loop-invariant coefficients in registers
+      for_row<TL>(nbr, st, i, nn, lane, [&](uint32_t ent) { pair(ent, pc0, false); });
+    } else {
+      for_row<TL>(nbr, st, i, nn, lane, [&](uint32_t ent) { pair(ent, ltab[0], true); });
     }
   }
 #pragma unroll
@@ -126,14 +141,23 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   if (own && lane == 0) {
     T *F = static_cast<T *>(a.force);
     const T Fx = (T)fx, Fy = (T)fy, Fz = (T)fz;
-    const double sc = a.mass ? a.accel / a.mass[i] : a.accel;
+    const double sc = FORCE_ONLY ? 0.0 : (a.mass ? a.accel / a.mass[i] : a.accel);
     const double hx = a.half_dt * (double)Fx, hy = a.half_dt * (double)Fy, hz = a.half_dt * (double)Fz;
-    double vx = a.vel[i], vy = a.vel[st + i], vz = a.vel[2 * st + i];
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (!FORCE_ONLY) {
+      vx = a.vel[i];
+      vy = a.vel[st + i];
+      vz = a.vel[2 * st + i];
+    }
     // explicit fused multiply-adds: every kick and drift rounds the same way in every kernel
     vx = fma(hx, sc, vx);
     vy = fma(hy, sc, vy);
     vz = fma(hz, sc, vz);
-    if (MODE == kStepMid) {
+    if (FORCE_ONLY) {
+      F[i] = Fx;
+      F[st + i] = Fy;
+      F[2 * st + i] = Fz;
+    } else if (MODE == kStepMid) {
       vx = fma(hx, sc, vx);
       vy = fma(hy, sc, vy);
       vz = fma(hz, sc, vz);
@@ -154,9 +178,11 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
         a.pos_final[2 * st + i] = rz;
       }
     }
-    a.vel[i] = vx;
-    a.vel[st + i] = vy;
-    a.vel[2 * st + i] = vz;
+    if (!FORCE_ONLY) {
+      a.vel[i] = vx;
+      a.vel[st + i] = vy;
+      a.vel[2 * st + i] = vz;
+    }
   }
   if (MODE == kStepMid && blockIdx.x == 0 && tid == 0) {
     a.flag_clear[s] = 0;
@@ -185,62 +211,70 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   }
 }
 
-// Rebuild rows: one wavefront per atom; a workgroup of 16 wavefronts handles 16 consecutive atoms
-// of one flagged system ("chunks" of 16 atoms; chunks_per_sys covers the largest system).
-constexpr int kRebuildWaves = 16;
+// Rebuild rows: one wavefront per atom; a workgroup of kRebuildWaves wavefronts handles that many
+// consecutive atoms of one flagged system ("chunks"; chunks_per_sys covers the largest system).
+constexpr int kRebuildWaves = 8;
 
-__global__ void __launch_bounds__(1024) k_rebuild_rows(StepArgs a, int chunks_per_sys) {
+// Candidate images of one (i, j) pair along one lattice direction: integers S with
+// |ds + S| < reach (+ a rounding margin), ds the fractional difference.
+__device__ inline void image_range(double f, double reach, int *lo, int *hi) {
+  *lo = (int)ceil(-f - reach - 1e-9);
+  *hi = (int)floor(-f + reach + 1e-9);
+}
+
+__device__ inline bool shift_ok(int S0, int S1, int S2) {
+  return S0 >= -TS_MAX_IMAGE_SHIFT && S0 <= TS_MAX_IMAGE_SHIFT && S1 >= -TS_MAX_IMAGE_SHIFT &&
+         S1 <= TS_MAX_IMAGE_SHIFT && S2 >= -TS_MAX_IMAGE_SHIFT && S2 <= TS_MAX_IMAGE_SHIFT;
+}
+
+__global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs a, int chunks_per_sys) {
   extern __shared__ double lds[];
-  __shared__ double geo[12];
   const int n_flag = *a.count_cur;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const double rl2 = a.r_list * a.r_list;
   const int64_t st = a.st_vel;
+  const double *__restrict__ pin = a.pos_in;
+  uint32_t *__restrict__ nbr = a.nbr;
   for (int chunk = blockIdx.x; chunk < n_flag * chunks_per_sys; chunk += gridDim.x) {
     const int s = a.list_cur[chunk / chunks_per_sys];
     const int c0 = (chunk % chunks_per_sys) * kRebuildWaves;
     const int64_t a0 = a.offs[s];
     const int ns = (int)(a.offs[s + 1] - a0);
     if (c0 >= ns) continue;  // uniform over the workgroup
-    const double *h = a.cell + 9 * (int64_t)s;
-    __syncthreads();  // the previous chunk's readers are done with lds and geo
+    const double *__restrict__ h = a.cell + 9 * (int64_t)s;
+    __syncthreads();  // the previous chunk's readers are done with lds
     double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
     for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-      lx[k] = a.pos_in[a0 + k];
-      ly[k] = a.pos_in[a.st_in + a0 + k];
-      lz[k] = a.pos_in[2 * a.st_in + a0 + k];
+      lx[k] = pin[a0 + k];
+      ly[k] = pin[a.st_in + a0 + k];
+      lz[k] = pin[2 * a.st_in + a0 + k];
     }
-    if (threadIdx.x == 0) {
-      const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
-                         h[2] * (h[3] * h[7] - h[4] * h[6]);
-      const double id = 1.0 / det;
-      geo[0] = (h[4] * h[8] - h[5] * h[7]) * id;
-      geo[1] = (h[2] * h[7] - h[1] * h[8]) * id;
-      geo[2] = (h[1] * h[5] - h[2] * h[4]) * id;
-      geo[3] = (h[5] * h[6] - h[3] * h[8]) * id;
-      geo[4] = (h[0] * h[8] - h[2] * h[6]) * id;
-      geo[5] = (h[2] * h[3] - h[0] * h[5]) * id;
-      geo[6] = (h[3] * h[7] - h[4] * h[6]) * id;
-      geo[7] = (h[1] * h[6] - h[0] * h[7]) * id;
-      geo[8] = (h[0] * h[4] - h[1] * h[3]) * id;
-      const double vol = fabs(det);
-      for (int k = 0; k < 3; ++k) {
-        const double *p = h + 3 * ((k + 1) % 3);
-        const double *q = h + 3 * ((k + 2) % 3);
-        const double cx = p[1] * q[2] - p[2] * q[1], cy = p[2] * q[0] - p[0] * q[2], cz = p[0] * q[1] - p[1] * q[0];
-        geo[9 + k] = a.r_list / (vol / sqrt(cx * cx + cy * cy + cz * cz));
-      }
-      if (c0 == 0) {
-        for (int k = 0; k < 9; ++k) a.ref_cell[9 * (int64_t)s + k] = h[k];
-        atomicAdd((unsigned long long *)&a.status[TS_STATUS_REBUILDS], 1ull);
-      }
+    if (c0 == 0) {
+      if (threadIdx.x < 9) a.ref_cell[9 * (int64_t)s + threadIdx.x] = h[threadIdx.x];
+      if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.status[TS_STATUS_REBUILDS], 1ull);
     }
+    // cell, inverse and reach: uniform values every lane computes itself (no serial section)
+    const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
+                 h22 = h[8];
+    const double det = h00 * (h11 * h22 - h12 * h21) - h01 * (h10 * h22 - h12 * h20) + h02 * (h10 * h21 - h11 * h20);
+    const double id = 1.0 / det;
+    const double i00 = (h11 * h22 - h12 * h21) * id, i01 = (h02 * h21 - h01 * h22) * id,
+                 i02 = (h01 * h12 - h02 * h11) * id, i10 = (h12 * h20 - h10 * h22) * id,
+                 i11 = (h00 * h22 - h02 * h20) * id, i12 = (h02 * h10 - h00 * h12) * id,
+                 i20 = (h10 * h21 - h11 * h20) * id, i21 = (h01 * h20 - h00 * h21) * id,
+                 i22 = (h00 * h11 - h01 * h10) * id;
+    const double vol = fabs(det);
+    // reach_k = r_list / w_k with w_k = V / |a_{k+1} x a_{k+2}|
+    const double c0x = h11 * h22 - h12 * h21, c0y = h12 * h20 - h10 * h22, c0z = h10 * h21 - h11 * h20;
+    const double c1x = h21 * h02 - h22 * h01, c1y = h22 * h00 - h20 * h02, c1z = h20 * h01 - h21 * h00;
+    const double c2x = h01 * h12 - h02 * h11, c2y = h02 * h10 - h00 * h12, c2z = h00 * h11 - h01 * h10;
+    const double re0 = a.r_list / (vol / sqrt(c0x * c0x + c0y * c0y + c0z * c0z));
+    const double re1 = a.r_list / (vol / sqrt(c1x * c1x + c1y * c1y + c1z * c1z));
+    const double re2 = a.r_list / (vol / sqrt(c2x * c2x + c2y * c2y + c2z * c2z));
     __syncthreads();
     const int li = c0 + wave;
     if (li >= ns) continue;  // uniform over the wavefront; no block barrier follows before the loop top
     const int64_t i = a0 + li;
-    const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
-                 h22 = h[8];
     const double rx = lx[li], ry = ly[li], rz = lz[li];
     int cnt = 0;
     bool shift_bad = false;
@@ -254,41 +288,50 @@ __global__ void __launch_bounds__(1024) k_rebuild_rows(StepArgs a, int chunks_pe
         drx = lx[j] - rx;
         dry = ly[j] - ry;
         drz = lz[j] - rz;
-        // images S with |ds_k + S_k| w_k < r_list along every direction (ds: fractional difference)
-        const double f0 = drx * geo[0] + dry * geo[3] + drz * geo[6];
-        const double f1 = drx * geo[1] + dry * geo[4] + drz * geo[7];
-        const double f2 = drx * geo[2] + dry * geo[5] + drz * geo[8];
-        lo0 = (int)ceil(-f0 - geo[9] - 1e-9);
-        hi0 = (int)floor(-f0 + geo[9] + 1e-9);
-        lo1 = (int)ceil(-f1 - geo[10] - 1e-9);
-        hi1 = (int)floor(-f1 + geo[10] + 1e-9);
-        lo2 = (int)ceil(-f2 - geo[11] - 1e-9);
-        hi2 = (int)floor(-f2 + geo[11] + 1e-9);
-        for (int S0 = lo0; S0 <= hi0; ++S0)
-          for (int S1 = lo1; S1 <= hi1; ++S1)
-            for (int S2 = lo2; S2 <= hi2; ++S2) {
-              if (j == li && S0 == 0 && S1 == 0 && S2 == 0) continue;
-              const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
-              const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
-              const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
-              if (!(norm2(dx, dy, dz) < rl2)) continue;
-              if (a.half) {
-                const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
-                if (!(li < j || (li == j && fs > 0))) continue;
-              }
-              if (S0 < -TS_MAX_IMAGE_SHIFT || S0 > TS_MAX_IMAGE_SHIFT || S1 < -TS_MAX_IMAGE_SHIFT ||
-                  S1 > TS_MAX_IMAGE_SHIFT || S2 < -TS_MAX_IMAGE_SHIFT || S2 > TS_MAX_IMAGE_SHIFT) {
+        image_range(drx * i00 + dry * i10 + drz * i20, re0, &lo0, &hi0);
+        image_range(drx * i01 + dry * i11 + drz * i21, re1, &lo1, &hi1);
+        image_range(drx * i02 + dry * i12 + drz * i22, re2, &lo2, &hi2);
+        if (lo0 == hi0 && lo1 == hi1 && lo2 == hi2) {
+          // one candidate image (always the case when the cell is wider than 2 r_list)
+          const int S0 = lo0, S1 = lo1, S2 = lo2;
+          if (!(j == li && S0 == 0 && S1 == 0 && S2 == 0)) {
+            const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+            const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+            const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+            const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
+            if (norm2(dx, dy, dz) < rl2 && (!a.half || li < j || (li == j && fs > 0))) {
+              if (shift_ok(S0, S1, S2)) {
+                e1 = pack_entry(j, S0, S1, S2);
+                c = 1;
+              } else {
                 shift_bad = true;
-                continue;
               }
-              if (c == 0) e1 = pack_entry(j, S0, S1, S2);
-              ++c;
             }
+          }
+        } else {
+          for (int S0 = lo0; S0 <= hi0; ++S0)
+            for (int S1 = lo1; S1 <= hi1; ++S1)
+              for (int S2 = lo2; S2 <= hi2; ++S2) {
+                if (j == li && S0 == 0 && S1 == 0 && S2 == 0) continue;
+                const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+                const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+                const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+                if (!(norm2(dx, dy, dz) < rl2)) continue;
+                const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
+                if (a.half && !(li < j || (li == j && fs > 0))) continue;
+                if (!shift_ok(S0, S1, S2)) {
+                  shift_bad = true;
+                  continue;
+                }
+                if (c == 0) e1 = pack_entry(j, S0, S1, S2);
+                ++c;
+              }
+        }
       }
-      // exclusive prefix of the per-lane counts across the wavefront
+      // exclusive prefix of the per-lane counts across the wavefront (ballot + mbcnt when every
+      // lane holds at most one entry)
       int pre, total;
-      const uint64_t multi = __ballot(c > 1);
-      if (multi == 0) {
+      if (__ballot(c > 1) == 0) {
         const uint64_t one = __ballot(c == 1);
         pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(one >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)one, 0));
         total = __popcll(one);
@@ -304,7 +347,7 @@ __global__ void __launch_bounds__(1024) k_rebuild_rows(StepArgs a, int chunks_pe
       }
       int pos = cnt + pre;
       if (c == 1) {
-        if (pos < a.max_nbr) a.nbr[(int64_t)pos * st + i] = e1;
+        if (pos < a.max_nbr) nbr[row_index(pos, i, st)] = e1;
       } else if (c > 1) {
         for (int S0 = lo0; S0 <= hi0; ++S0)
           for (int S1 = lo1; S1 <= hi1; ++S1)
@@ -314,14 +357,10 @@ __global__ void __launch_bounds__(1024) k_rebuild_rows(StepArgs a, int chunks_pe
               const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
               const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
               if (!(norm2(dx, dy, dz) < rl2)) continue;
-              if (a.half) {
-                const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
-                if (!(li < j || (li == j && fs > 0))) continue;
-              }
-              if (S0 < -TS_MAX_IMAGE_SHIFT || S0 > TS_MAX_IMAGE_SHIFT || S1 < -TS_MAX_IMAGE_SHIFT ||
-                  S1 > TS_MAX_IMAGE_SHIFT || S2 < -TS_MAX_IMAGE_SHIFT || S2 > TS_MAX_IMAGE_SHIFT)
-                continue;
-              if (pos < a.max_nbr) a.nbr[(int64_t)pos * st + i] = pack_entry(j, S0, S1, S2);
+              const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
+              if (a.half && !(li < j || (li == j && fs > 0))) continue;
+              if (!shift_ok(S0, S1, S2)) continue;
+              if (pos < a.max_nbr) nbr[row_index(pos, i, st)] = pack_entry(j, S0, S1, S2);
               ++pos;
             }
       }
@@ -344,7 +383,7 @@ __global__ void __launch_bounds__(1024) k_rebuild_rows(StepArgs a, int chunks_pe
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st) {
   const int chunks = (int)ceil_div(max_atoms, kRebuildWaves);
   const int64_t work = n_sys * chunks;
-  const unsigned grid = (unsigned)(work < 1024 ? work : 1024);
+  const unsigned grid = (unsigned)(work < 2048 ? work : 2048);
   const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
   hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, a, chunks);
   TS_LAUNCH_CHECK();
@@ -357,8 +396,12 @@ static void launch_step_k(int mode, const StepArgs &a, const PairTable &t, dim3 
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepFirst>), g, dim3(256), 0, st, a, t);
   else if (mode == kStepMid)
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepMid>), g, dim3(256), shm, st, a, t);
-  else
+  else if (mode == kStepLast)
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLast>), g, dim3(256), shm, st, a, t);
+  else if (mode == kStepForce)
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepForce>), g, dim3(256), shm, st, a, t);
+  else
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepForceEV>), g, dim3(256), shm, st, a, t);
 }
 
 template <int KIND, typename T>

@@ -169,6 +169,14 @@ int ts_nve_step(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_param
                 int32_t n_steps, void *force, double *epot, double *ekin, double *virial, int32_t use_graph,
                 ts_stream_t stream);
 
+/* ts_nve_step that also records the trajectory: traj is device float64 [n_steps+1][3][n_atoms]
+   (compact structure-of-arrays, stride n_atoms) and receives r_0 .. r_{n_steps}; the batch ends at
+   r_{n_steps} as with ts_nve_step.  This is the forward recomputation of a checkpointed segment
+   for ts_adjoint_segment.  Systems of at most 2048 atoms (TS_E_UNSUPPORTED otherwise).
+   Graph caching as ts_nve_step. */
+int ts_nve_record(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_params *pp, double dt, double accel,
+                  int32_t n_steps, void *force, double *traj, int32_t use_graph, ts_stream_t stream);
+
 /* FIRE relaxation (Bitzek et al., PRL 97, 170201 (2006); the paper's structural relaxation
    optimizers, Abstract).  Per system and iteration: forces; stop if converged
    (max_i |F_i| < fmax, and with relax_cell also max |G_ab| < fmax); from the second iteration on
@@ -227,6 +235,18 @@ int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_fire_config 
 int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp, double dt_drift,
                     double w_kick, double accel, double *adj_pos, double *adj_vel, double *adj_params,
                     ts_stream_t stream);
+
+/* Reverse velocity-Verlet over one recorded segment r_{n0} .. r_{n0+n_steps} (traj as written by
+   ts_nve_record; the batch supplies masses, species and cells).  Positions are processed from
+   r_{n0+n_steps} down to r_{n0+1}, and also r_{n0} when bottom = 1 (n0 = 0); at each the adjoint
+   state advances as in ts_pair_adjoint with (dt_drift, w_kick) = (dt, dt), except (0, dt/2) at the
+   trajectory's last position when top = 1 and (dt, dt/2) at r_0 when bottom = 1.  Chaining the
+   segments from the last to the first (top = 1 on the last one, bottom = 1 on the first) is the
+   full reverse pass.  One launch per step (plus a rebuild launch that exits at once when no list
+   needs one); graph caching as ts_nve_step.  Systems of at most 2048 atoms. */
+int ts_adjoint_segment(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_params *pp, const double *traj,
+                       int32_t n_steps, double dt, double accel, int32_t top, int32_t bottom, double *adj_pos,
+                       double *adj_vel, double *adj_params, int32_t use_graph, ts_stream_t stream);
 
 /* Gaussian-smeared radial distribution function per system over the full pair set within r_max
    (the list's radius must be >= r_max):

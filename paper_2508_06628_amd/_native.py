@@ -119,6 +119,11 @@ SIGNATURES = {
                                  c_void_p, c_void_p, c_void_p]),
     "ts_nve_step": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double, c_double,
                               c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "ts_nve_record": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double,
+                                c_double, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "ts_adjoint_segment": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_void_p,
+                                     c_int32, c_double, c_double, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                     c_int32, c_void_p]),
     "ts_fire_step": (c_int32, [POINTER(TsBatch), POINTER(TsFireState), POINTER(TsFireConfig), POINTER(TsNeighborList),
                                POINTER(TsPairParams), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "ts_pair_adjoint": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double,

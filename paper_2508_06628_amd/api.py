@@ -261,6 +261,21 @@ def ts_nve_step(batch, nl, pp, dt, accel, n_steps, force, epot=None, ekin=None, 
                                                       1 if use_graph else 0, _stream(stream)))
 
 
+def ts_nve_record(batch, nl, pp, dt, accel, n_steps, force, traj, use_graph=True, stream=None):
+    return N.check("ts_nve_record", N.lib().ts_nve_record(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
+                                                          ctypes.byref(pp), float(dt), float(accel), int(n_steps),
+                                                          _p(force), _p(traj), 1 if use_graph else 0,
+                                                          _stream(stream)))
+
+
+def ts_adjoint_segment(batch, nl, pp, traj, n_steps, dt, accel, top, bottom, adj_pos, adj_vel, adj_params=None,
+                       use_graph=True, stream=None):
+    return N.check("ts_adjoint_segment", N.lib().ts_adjoint_segment(
+        ctypes.byref(batch.struct()), ctypes.byref(nl.struct()), ctypes.byref(pp), _p(traj), int(n_steps), float(dt),
+        float(accel), 1 if top else 0, 1 if bottom else 0, _p(adj_pos), _p(adj_vel), _p(adj_params),
+        1 if use_graph else 0, _stream(stream)))
+
+
 def ts_fire_step(batch, fs: FireState, cfg, nl, pp, n_iter, force, energy=None, virial=None, persistent=False,
                  stream=None):
     return N.check("ts_fire_step", N.lib().ts_fire_step(ctypes.byref(batch.struct()), ctypes.byref(fs.struct()),

@@ -27,6 +27,7 @@ struct NlWork {
   int32_t *fill;      // [2N+S] scatter cursors
   int32_t *perm;      // [N] atoms sorted by (system, bin, index)
   double *pos_alt;    // [3][N] second position buffer of the fused step loop
+  double *adj_alt;    // [6][N] second adjoint buffers (positions, velocities) of the reverse loop
   int32_t *flags3;    // fused step loop: rebuild flags [3][S], flagged lists [3][S], counts [3]
   size_t bytes;
 };

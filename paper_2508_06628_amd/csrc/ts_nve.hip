@@ -1,13 +1,11 @@
 // Velocity-Verlet NVE over the whole batch (the molecular-dynamics integrators of the paper's
 // Abstract; every system advances in the same launches, Section 3), with the per-step neighbor
 // validity test and rebuild on the device and an optional hipGraph of the whole step loop.
-#include <map>
-#include <mutex>
-#include <vector>
-
 #include <cstdlib>
+#include <string>
 
 #include "ts_forces.h"
+#include "ts_graph.h"
 #include "ts_neighbor.h"
 #include "ts_step.h"
 
@@ -15,7 +13,7 @@ namespace ts {
 
 // TS_NVE_UNFUSED=1 selects the multi-kernel step (separate list update, force and kick launches)
 // instead of the fused one; both compute the same trajectory.
-static bool fused_enabled() {
+bool fused_enabled() {
   const char *e = std::getenv("TS_NVE_UNFUSED");
   return !(e && e[0] == '1');
 }
@@ -115,9 +113,11 @@ static int nve_sequence_t(const ts_batch *b, ts_neighbor_list *nl, const PairTab
 }
 
 // One launch per step (see ts_step.hip): systems of at most kLdsMaxAtoms atoms, full list.
+// With traj != null every position r_0..r_N is written to traj ([N+1][3][n_atoms]), which then
+// serves as the ping-pong position storage of the loop.
 static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable &tab, int prec, double dt,
                               double accel, int n_steps, void *force, double *epot, double *ekin, double *virial,
-                              int64_t max_atoms, hipStream_t st) {
+                              int64_t max_atoms, hipStream_t st, double *traj = nullptr) {
   const int64_t n = b->n_atoms, S = b->n_systems;
   NlWork w = nl_work(nl->workspace, n, S);
   const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : 4;
@@ -169,6 +169,16 @@ static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const Pai
     a.count_next = w.flags3 + 6 * S + (step + 1) % 3;
     a.count_clear = w.flags3 + 6 * S + (step + 2) % 3;
     a.pos_final = (mode == kStepLast && step % 2 == 1) ? b->pos : nullptr;
+    a.n_atoms = n;
+    a.pos_copy = nullptr;
+    if (traj) {
+      a.pos_in = step == 0 ? b->pos : traj + 3 * n * step;
+      a.st_in = step == 0 ? stride_of(b) : n;
+      a.pos_out = traj + 3 * n * (step + 1);
+      a.st_out = n;
+      a.pos_copy = step == 0 ? traj : nullptr;
+      a.pos_final = mode == kStepLast ? b->pos : nullptr;
+    }
     a.epot = mode == kStepLast ? epot : nullptr;
     a.virial = mode == kStepLast ? virial : nullptr;
     if (mode != kStepFirst) {
@@ -196,67 +206,7 @@ static int nve_sequence(const ts_batch *b, ts_neighbor_list *nl, const ts_pair_p
   return nve_sequence_t<double>(b, nl, tab, pp->prec, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, st);
 }
 
-// ----------------------------------------------------------------------------- graph cache
-
-namespace {
-
-struct NveKey {
-  ts_batch b;
-  ts_neighbor_list nl;
-  ts_pair_params pp;
-  double dt, accel;
-  int64_t n_steps, max_atoms;
-  void *force;
-  double *epot, *ekin, *virial;
-  int device;
-};
-
-struct KeyLess {
-  bool operator()(const NveKey &x, const NveKey &y) const { return std::memcmp(&x, &y, sizeof(NveKey)) < 0; }
-};
-
-struct GraphEntry {
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  uint64_t stamp;
-};
-
-std::mutex g_mu;
-std::map<NveKey, GraphEntry, KeyLess> g_cache;
-uint64_t g_clock = 0;
-std::map<int, hipStream_t> g_capture_stream;
-constexpr size_t kMaxGraphs = 16;
-
-void destroy_entry(GraphEntry &e) {
-  (void)hipGraphExecDestroy(e.exec);
-  (void)hipGraphDestroy(e.graph);
-}
-
-}  // namespace
-
-int capture_stream(int device, hipStream_t *out) {
-  auto it = g_capture_stream.find(device);
-  if (it != g_capture_stream.end()) {
-    *out = it->second;
-    return TS_OK;
-  }
-  hipStream_t s;
-  TS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-  g_capture_stream[device] = s;
-  *out = s;
-  return TS_OK;
-}
-
-void release_graphs() {
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_cache.empty()) (void)hipDeviceSynchronize();
-  for (auto &kv : g_cache) destroy_entry(kv.second);
-  g_cache.clear();
-}
-
 }  // namespace ts
-
-extern "C" void ts_release_graphs(void) { ts::release_graphs(); }
 
 extern "C" int ts_kinetic_energy(const ts_batch *batch, double accel, double *ekin, ts_stream_t stream) {
   int rc = ts::validate_batch(batch, true, nullptr);
@@ -273,55 +223,47 @@ extern "C" int ts_nve_step(const ts_batch *batch, ts_neighbor_list *nl, const ts
   if (rc != TS_OK) return rc;
   TS_CHECK_ARG(force != nullptr);
   TS_CHECK_ARG(std::isfinite(dt) && dt > 0.0 && std::isfinite(accel) && accel > 0.0 && n_steps >= 0);
-  hipStream_t st = ts::as_stream(stream);
-  if (!use_graph) return ts::nve_sequence(batch, nl, pp, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, st);
+  std::string key("nve");
+  ts::key_add(key, *batch);
+  ts::key_add(key, *nl);
+  ts::key_add(key, *pp);
+  ts::key_add(key, dt);
+  ts::key_add(key, accel);
+  ts::key_add(key, n_steps);
+  ts::key_add(key, max_atoms);
+  ts::key_add(key, force);
+  ts::key_add(key, epot);
+  ts::key_add(key, ekin);
+  ts::key_add(key, virial);
+  const bool fused = ts::fused_enabled();
+  ts::key_add(key, fused);
+  return ts::run_graph_cached(use_graph != 0, key, ts::as_stream(stream), [&](hipStream_t s) {
+    return ts::nve_sequence(batch, nl, pp, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, s);
+  });
+}
 
-  ts::NveKey key;
-  std::memset(&key, 0, sizeof(key));
-  key.b = *batch;
-  key.nl = *nl;
-  key.pp = *pp;
-  key.dt = dt;
-  key.accel = accel;
-  key.n_steps = n_steps;
-  key.max_atoms = max_atoms;
-  key.force = force;
-  key.epot = epot;
-  key.ekin = ekin;
-  key.virial = virial;
-  TS_HIP(hipGetDevice(&key.device));
-
-  std::lock_guard<std::mutex> lk(ts::g_mu);
-  auto it = ts::g_cache.find(key);
-  if (it == ts::g_cache.end()) {
-    hipStream_t cap;
-    rc = ts::capture_stream(key.device, &cap);
-    if (rc != TS_OK) return rc;
-    TS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    rc = ts::nve_sequence(batch, nl, pp, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, cap);
-    hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(cap, &graph);
-    if (rc != TS_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
-    }
-    if (ce != hipSuccess || graph == nullptr) return TS_E_HIP;
-    hipGraphExec_t exec;
-    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return TS_E_HIP;
-    }
-    if (ts::g_cache.size() >= ts::kMaxGraphs) {
-      auto old = ts::g_cache.begin();
-      for (auto jt = ts::g_cache.begin(); jt != ts::g_cache.end(); ++jt)
-        if (jt->second.stamp < old->second.stamp) old = jt;
-      (void)hipDeviceSynchronize();
-      ts::destroy_entry(old->second);
-      ts::g_cache.erase(old);
-    }
-    it = ts::g_cache.emplace(key, ts::GraphEntry{graph, exec, 0}).first;
-  }
-  it->second.stamp = ++ts::g_clock;
-  TS_HIP(hipGraphLaunch(it->second.exec, st));
-  return TS_OK;
+extern "C" int ts_nve_record(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_params *pp, double dt,
+                             double accel, int32_t n_steps, void *force, double *traj, int32_t use_graph,
+                             ts_stream_t stream) {
+  int64_t max_atoms = 0;
+  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, true);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(force != nullptr && traj != nullptr);
+  TS_CHECK_ARG(std::isfinite(dt) && dt > 0.0 && std::isfinite(accel) && accel > 0.0 && n_steps >= 1);
+  if (max_atoms > ts::kLdsMaxAtoms || nl->half || batch->n_atoms == 0) return TS_E_UNSUPPORTED;
+  std::string key("record");
+  ts::key_add(key, *batch);
+  ts::key_add(key, *nl);
+  ts::key_add(key, *pp);
+  ts::key_add(key, dt);
+  ts::key_add(key, accel);
+  ts::key_add(key, n_steps);
+  ts::key_add(key, max_atoms);
+  ts::key_add(key, force);
+  ts::key_add(key, traj);
+  const ts::PairTable tab = ts::make_table(pp);
+  return ts::run_graph_cached(use_graph != 0, key, ts::as_stream(stream), [&](hipStream_t s) {
+    return ts::nve_fused_sequence(batch, nl, tab, pp->prec, dt, accel, n_steps, force, nullptr, nullptr, nullptr,
+                                  max_atoms, s, traj);
+  });
 }

@@ -19,6 +19,8 @@ struct StepArgs {
   double *pos_out;  // r_{n+1}
   int64_t st_out;
   double *pos_final;  // last step: where r_N is copied (the caller's buffer), or null
+  double *pos_copy;   // first step: where r_0 is copied (compact stride n_atoms), or null
+  int64_t n_atoms;
   double *vel;        // velocities, forces, list rows and reference positions use st_vel
   int64_t st_vel;
   const double *mass;

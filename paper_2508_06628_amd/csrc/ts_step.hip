@@ -51,7 +51,9 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
       for (int c = 0; c < 3; ++c) {
         const double v = fma(a.half_dt * (double)F[c * a.st_vel + i], sc, a.vel[c * a.st_vel + i]);
         a.vel[c * a.st_vel + i] = v;
-        r[c] = fma(a.dt, v, a.pos_in[c * a.st_in + i]);
+        const double r0 = a.pos_in[c * a.st_in + i];
+        if (a.pos_copy) a.pos_copy[c * a.n_atoms + i] = r0;
+        r[c] = fma(a.dt, v, r0);
         a.pos_out[c * a.st_out + i] = r[c];
       }
       if (list_invalid(r, a.ref_pos, a.st_vel, i, h, a.ref_cell + 9 * (int64_t)s, a.skin, a.r_list))

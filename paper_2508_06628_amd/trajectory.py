@@ -98,8 +98,39 @@ class TrajectoryRDF:
         api.ts_rdf_loss(self.g, self.target, self.loss, self.dl_dg)
         return self.loss
 
-    def backward(self):
-        """(dL/deps, dL/dsigma, dL/dr_0 (3, N)) for the last forward()."""
+    def backward(self, fused: bool = True):
+        """(dL/deps, dL/dsigma, dL/dr_0 (3, N)) for the last forward().  ``fused`` uses the recorded
+        segment entry points (systems of at most 2048 atoms); otherwise one call per step."""
+        if fused and self.batch.max_system_atoms <= 2048:
+            return self._backward_segments()
+        return self._backward_steps()
+
+    def _backward_segments(self):
+        eps, sigma = self.params
+        pp = self._pp(eps, sigma)
+        b, dt, accel = self.batch, self.w.dt, self.w.accel
+        r = self.rdf
+        lr = torch.zeros_like(b.pos)
+        lv = torch.zeros_like(b.pos)
+        tb = torch.zeros(48, dtype=torch.float64, device=b.device)
+        api.ts_rdf_vjp(b, self.nl_rdf, r.n_bins, r.r_end, r.sigma, r.r_max, self.dl_dg, lr)
+        n = b.n_atoms
+        if getattr(self, "_traj", None) is None or self._traj.shape[0] < self.K + 1:
+            self._traj = torch.empty((self.K + 1, 3, n), dtype=torch.float64, device=b.device)
+        n_seg = len(self.checkpoints)
+        for seg in range(n_seg - 1, -1, -1):
+            p0, v0 = self.checkpoints[seg]
+            k = min(self.K, self.n_steps - seg * self.K)
+            b.pos.copy_(p0)
+            b.vel.copy_(v0)
+            api.ts_neighbor_build(b, self.nl, force=True)
+            api.ts_pair_forces(b, self.nl, pp, self.force)
+            api.ts_nve_record(b, self.nl, pp, dt, accel, k, self.force, self._traj)
+            api.ts_adjoint_segment(b, self.nl, pp, self._traj, k, dt, accel, seg == n_seg - 1, seg == 0, lr, lv, tb)
+        grads = tb.cpu().numpy()
+        return float(grads[0]), float(grads[1]), lr
+
+    def _backward_steps(self):
         eps, sigma = self.params
         pp = self._pp(eps, sigma)
         b, dt, accel = self.batch, self.w.dt, self.w.accel

@@ -50,13 +50,14 @@ def _engine(w, prec):
     return eng
 
 
-def test_gradient_fp64_matches_oracle_reverse_pass(problem):
+@pytest.mark.parametrize("fused", [True, False])
+def test_gradient_fp64_matches_oracle_reverse_pass(problem, fused):
     w, eps, sig, target, (loss_ref, lr0_ref, de_ref, ds_ref) = problem
     eng = _engine(w, "f64")
     eng.set_target(torch.tensor(target, device="cuda"))
     pos0 = eng.batch.pos.clone()
     loss = eng.forward(eps, sig, pos0).item()
-    de, ds, lr0 = eng.backward()
+    de, ds, lr0 = eng.backward(fused=fused)
     assert abs(loss - loss_ref) <= 1e-9 * abs(loss_ref)
     assert abs(de - de_ref) <= 1e-8 * abs(de_ref)
     assert abs(ds - ds_ref) <= 1e-8 * abs(ds_ref)
@@ -121,3 +122,26 @@ def test_autograd_function_routes_through_the_engine(problem):
     assert abs(e_t.grad.item() - de_ref) <= 1e-8 * abs(de_ref)
     assert abs(s_t.grad.item() - ds_ref) <= 1e-8 * abs(ds_ref)
     assert np.abs(p_t.grad.T.cpu().numpy() - lr0_ref).max() <= 1e-8 * np.abs(lr0_ref).max()
+
+
+def test_recorded_segment_equals_step_loop():
+    # ts_nve_record reproduces ts_nve_step bit for bit and stores every position
+    from paper_2508_06628_amd import api
+    w = _workload()
+    outs = []
+    for record in (False, True):
+        b = api.Batch.from_workload(w)
+        nl = api.build_neighbor_list(b, w.potential.cutoff, 0.3)
+        pp = api.pair_params_from_spec(w.potential, "f32")
+        F = api.force_buffer(b, "f32")
+        api.ts_pair_forces(b, nl, pp, F)
+        if record:
+            traj = torch.zeros((13, 3, b.n_atoms), dtype=torch.float64, device="cuda")
+            api.ts_nve_record(b, nl, pp, w.dt, w.accel, 12, F, traj)
+            assert torch.equal(traj[0], torch.tensor(w.pos.T.copy(), device="cuda"))
+            assert torch.equal(traj[12], b.pos)
+        else:
+            api.ts_nve_step(b, nl, pp, w.dt, w.accel, 12, F)
+        outs.append((b.pos.clone(), b.vel.clone(), F.clone()))
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)

@@ -7,6 +7,7 @@ plain one-system-per-launch path on the same GPU, the adjoint (trajectory-gradie
 of the 16 x 864 differentiable run, and the FP64 CPU oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--chunk C] [--no-plain] [--no-adjoint] [--no-cpu]
+    python bench.py --profile-kernels --lanes L     # short launch sequence for rocprofv3
 """
 from __future__ import annotations
 
@@ -73,29 +74,36 @@ def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes):
 
 
 def force_kernel_roofline(api, torch, r, reps=200):
-    """Average duration of the pair-force kernel alone (the NVE loop's variant: forces only),
-    timed with events on the stream it is launched on, and its algorithmic HBM bytes."""
+    """Average duration of the pair-force kernel alone, timed with events on the stream it is
+    launched on (torch's current stream), and its algorithmic HBM bytes.  For systems that fit the
+    LDS (up to 2048 atoms) the force entry point runs the step kernel in its forces-only mode: one
+    workgroup per system, positions staged in LDS."""
     b, nl, pp, F = r["batch"], r["nl"], r["pp"], r["F"]
+    stream = torch.cuda.current_stream()
     for _ in range(10):
-        api.ts_pair_forces(b, nl, pp, F)
+        api.ts_pair_forces(b, nl, pp, F, stream=stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(stream)
     for _ in range(reps):
-        api.ts_pair_forces(b, nl, pp, F)
-    e1.record()
+        api.ts_pair_forces(b, nl, pp, F, stream=stream)
+    e1.record(stream)
     torch.cuda.synchronize()
     avg_ms = e0.elapsed_time(e1) / reps
-    n = b.n_atoms
+    n, n_sys = b.n_atoms, b.n_systems
     entries = int(nl.n_nbr.sum().item())
     fbytes = 4 if F.dtype == torch.float32 else 8
-    # per atom: position 24 B, list length 4 B, system index 4 B, force 3*fbytes; per entry 4 B
-    alg = n * (24 + 4 + 4 + 3 * fbytes) + 4 * entries
+    # per atom: position 24 B, list length 4 B, force 3*fbytes; per list entry 4 B;
+    # per system: atom offset 8 B and cell 72 B
+    alg = n * (24 + 4 + 3 * fbytes) + 4 * entries + n_sys * (8 + 72)
     achieved = alg / (avg_ms * 1e-3) / 1e9
+    tl = nl.lanes_per_atom if nl.lanes_per_atom > 0 else 4
+    ftype = "float" if fbytes == 4 else "double"
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel="k_pair_forces<LJ,float,EV=0>",
-                avg_launch_us=round(avg_ms * 1e3, 3), alg_bytes_per_launch=alg,
-                alg_bytes_per_atom=round(alg / n, 1), mean_list_len=round(entries / n, 2))
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=f"ts::k_step<0, {ftype}, {tl}, 3>", avg_launch_us=round(avg_ms * 1e3, 3),
+                launches_timed=reps, alg_bytes_per_launch=alg, alg_bytes_per_atom=round(alg / n, 1),
+                mean_list_len=round(entries / n, 2))
 
 
 def plain_path(api, torch, w, steps, bin_factor):
@@ -158,6 +166,30 @@ def cpu_baseline(w, steps=2):
                        f"{dt:.1f} s, single process float64 NumPy")
 
 
+def profile_kernels(api, torch, w, lanes, bin_factor, reps=20, copy_mib=256):
+    """Fixed launch sequence for rocprofv3 runs (kernel trace and byte counters): the force
+    kernel ``reps`` times, two 100-step NVE graph replays, and a plain device copy of
+    ``copy_mib`` MiB whose counter readings calibrate the byte counters."""
+    b = api.Batch.from_workload(w)
+    pot = w.potential
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
+    nl.lanes_per_atom = lanes
+    pp = api.pair_params_from_spec(pot, w.pair_prec)
+    F = api.force_buffer(b, w.pair_prec)
+    for _ in range(reps):
+        api.ts_pair_forces(b, nl, pp, F)
+    for _ in range(2):
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, 100, F, use_graph=True)
+    n = copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return dict(mode="profile", workload=w.name, n_atoms=b.n_atoms, lanes_per_atom=lanes, force_launches=reps,
+                list_entries=int(nl.n_nbr.sum().item()), copy_bytes_each_way=n * 4, copy_launches=3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +203,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="run a short fixed launch sequence for rocprofv3 instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (systems would shard "
@@ -184,6 +218,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     w = argon_batch(64, seed=1, n_steps=args.steps)
     log(f"workload {w.name}: {w.n_systems} systems, {w.n_atoms} atoms")
+    if args.profile_kernels:
+        print(json.dumps(profile_kernels(api, torch, w, args.lanes or 4, args.bin_factor)), flush=True)
+        return
     r = batched_nve(api, torch, w, args.steps, args.warmup, args.chunk, args.bin_factor, args.lanes)
     ms_per_step = r["ms"] / args.steps
     value = w.n_atoms * args.steps / (r["ms"] * 1e-3)

@@ -120,6 +120,10 @@ typedef struct {
   int32_t bin_factor;  /* cell-list bins per list radius along each direction (1..4) */
   int32_t lanes_per_atom; /* lanes of a wavefront sharing one atom's row in the fused step
                              kernels: 1, 2, 4 or 8 (0 = 4) */
+  int32_t group_atoms;  /* atoms one 256-lane workgroup of the fused step kernels owns (its system's
+                           positions are staged in LDS once for all of them): rounded down to a
+                           multiple of 256 / lanes_per_atom; 0 = chosen from the batch shape */
+  int32_t reserved;     /* must be 0 */
   int32_t *nbr;        /* device [ceil(max_nbr / 8)][stride][8] */
   int32_t *n_nbr;      /* device [N] */
   double *ref_pos;     /* device SoA [3][stride]: positions at the last build of each system */

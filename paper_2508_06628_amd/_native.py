@@ -71,6 +71,8 @@ class TsNeighborList(ctypes.Structure):
         ("max_nbr", c_int32),
         ("bin_factor", c_int32),
         ("lanes_per_atom", c_int32),
+        ("group_atoms", c_int32),
+        ("reserved", c_int32),
         ("nbr", c_void_p),
         ("n_nbr", c_void_p),
         ("ref_pos", c_void_p),

@@ -119,9 +119,10 @@ class NeighborList:
     """Padded neighbor list of a batch (rows of packed (j, S) entries, blocks of 8 per atom)."""
 
     def __init__(self, batch: Batch, cutoff: float, skin: float, max_nbr: int, bin_factor: int = 1, half: bool = False,
-                 lanes_per_atom: int = 0):
+                 lanes_per_atom: int = 0, group_atoms: int = 0):
         self.cutoff, self.skin, self.half, self.bin_factor = float(cutoff), float(skin), bool(half), int(bin_factor)
         self.lanes_per_atom = int(lanes_per_atom)
+        self.group_atoms = int(group_atoms)
         self.n_atoms, self.n_systems = batch.n_atoms, batch.n_systems
         self._alloc(batch, int(max_nbr))
 
@@ -146,6 +147,7 @@ class NeighborList:
         s.max_nbr = self.max_nbr
         s.bin_factor = self.bin_factor
         s.lanes_per_atom = self.lanes_per_atom
+        s.group_atoms = self.group_atoms
         s.nbr = self.nbr.data_ptr()
         s.n_nbr = self.n_nbr.data_ptr()
         s.ref_pos = self.ref_pos.data_ptr()
@@ -184,10 +186,11 @@ def estimate_max_nbr(batch: Batch, r_list: float, margin: float = 1.3) -> int:
 
 
 def build_neighbor_list(batch: Batch, cutoff: float, skin: float, bin_factor: int = 1, max_nbr: Optional[int] = None,
-                        margin: float = 1.25, half: bool = False, lanes_per_atom: int = 0) -> NeighborList:
+                        margin: float = 1.25, half: bool = False, lanes_per_atom: int = 0,
+                        group_atoms: int = 0) -> NeighborList:
     """Allocate and build a list, regrowing once if the first capacity guess was too small."""
     guess = max_nbr or estimate_max_nbr(batch, cutoff + skin)
-    nl = NeighborList(batch, cutoff, skin, guess, bin_factor, half, lanes_per_atom)
+    nl = NeighborList(batch, cutoff, skin, guess, bin_factor, half, lanes_per_atom, group_atoms)
     ts_neighbor_build(batch, nl, force=True)
     st = nl.read_status()
     if st[N.TS_STATUS_NONFINITE] or st[N.TS_STATUS_SHIFT]:

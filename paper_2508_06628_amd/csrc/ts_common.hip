@@ -49,6 +49,7 @@ int validate_list(const ts_batch *b, const ts_neighbor_list *nl) {
   TS_CHECK_ARG(nl->bin_factor >= 1 && nl->bin_factor <= 4);
   TS_CHECK_ARG(nl->lanes_per_atom == 0 || nl->lanes_per_atom == 1 || nl->lanes_per_atom == 2 ||
                nl->lanes_per_atom == 4 || nl->lanes_per_atom == 8);
+  TS_CHECK_ARG(nl->group_atoms >= 0 && nl->reserved == 0);
   TS_CHECK_ARG(nl->nbr && nl->n_nbr && nl->ref_pos && nl->ref_cell && nl->status && nl->workspace);
   TS_CHECK_ARG(nl->workspace_bytes >= ts_neighbor_workspace_bytes(b->n_atoms, b->n_systems));
   return TS_OK;

@@ -189,7 +189,8 @@ extern "C" int ts_pair_forces(const ts_batch *batch, const ts_neighbor_list *nl,
     s.virial = virial;
     const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : 4;
     const int mode = (energy || virial) ? ts::kStepForceEV : ts::kStepForce;
-    return ts::launch_step(mode, tl, s, t, pp->prec, batch->n_systems, max_atoms, st);
+    return ts::launch_step(mode, tl, nl->group_atoms, s, t, pp->prec, batch->n_systems, max_atoms,
+                           batch->h_sys_offsets, st);
   }
   const ts::ForceArgs a = ts::make_force_args(batch, nl, force, energy, virial, nullptr);
   return ts::launch_forces(a, batch->n_systems, t, pp->prec, energy != nullptr || virial != nullptr,

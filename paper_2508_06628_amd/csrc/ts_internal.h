@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "ts_api.h"
 
@@ -70,6 +71,15 @@ __host__ __device__ inline int64_t row_index(int k, int64_t i, int64_t st) {
 __device__ inline double shift_comp(double dr, double S0, double S1, double S2, double h0c, double h1c, double h2c) {
   return dr + fma(S2, h2c, fma(S1, h1c, S0 * h0c));
 }
+// Workgroups go to the 8 XCDs of the chip round-robin by workgroup number.  The renumbering
+// b -> (b mod 8) * (grid / 8) + b / 8 hands XCD x the consecutive range [x grid/8, (x+1) grid/8), so
+// workgroups that share data (those of one system) sit behind one L2.  It is a bijection of
+// [0, grid) when grid is a multiple of 8.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_order(int64_t b, int64_t grid) {
+  return (b % kXcds) * (grid / kXcds) + b / kXcds;
+}
+
 __device__ inline double norm2(double dx, double dy, double dz) { return fma(dz, dz, fma(dy, dy, dx * dx)); }
 
 // ----------------------------------------------------------------------------- pair tables
@@ -115,6 +125,33 @@ __device__ inline void for_row(const uint32_t *__restrict__ nbr, int64_t st, int
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (k + u * TL < nn) f(cur[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+  }
+}
+
+// Visit the same entries as for_row, U visits at a time: f(ent, ok) receives U consecutive entries
+// of the lane (ok[u] false past the end of the row, with ent[u] = 0) and evaluates them without
+// branches between them, so the U dependent chains can be interleaved.  Results must be combined
+// in u order to sum like the plain loop.
+template <int TL, int U, typename F>
+__device__ inline void for_row_batched(const uint32_t *__restrict__ nbr, int64_t st, int64_t i, int nn, int lane,
+                                       F &&f) {
+  uint32_t cur[U], nxt[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int kk = lane + u * TL;
+    cur[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
+  }
+  for (int k = lane; k < nn; k += U * TL) {
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = k + (U + u) * TL;
+      nxt[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
+      ok[u] = k + u * TL < nn;
+    }
+    f(cur, ok);
 #pragma unroll
     for (int u = 0; u < U; ++u) cur[u] = nxt[u];
   }

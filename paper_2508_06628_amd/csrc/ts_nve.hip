@@ -185,7 +185,7 @@ static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const Pai
       rc = launch_rebuild(a, S, max_atoms, st);
       if (rc != TS_OK) return rc;
     }
-    rc = launch_step(mode, tl, a, tab, prec, S, max_atoms, st);
+    rc = launch_step(mode, tl, nl->group_atoms, a, tab, prec, S, max_atoms, b->h_sys_offsets, st);
     if (rc != TS_OK) return rc;
   }
   if (ekin) {

@@ -10,6 +10,7 @@ constexpr int kStepMid = 1;    // forces, two half kicks, drift, validity test
 constexpr int kStepLast = 2;   // forces (+ energy, virial), last half kick
 constexpr int kStepForce = 3;  // forces only (ts_pair_forces)
 constexpr int kStepForceEV = 4;  // forces, energy and virial (ts_pair_forces)
+constexpr int kStepUnroll = 4;      // row entries a lane evaluates together in the step kernel
 constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)
 
 struct StepArgs {
@@ -40,7 +41,13 @@ struct StepArgs {
   double r_list, skin;
   double half_dt, dt, accel;
   double *epot, *virial;
+  int chunks;      // workgroups per system; each owns rounds * 256/TL consecutive atoms
+  int rounds;
+  int64_t n_work;  // n_systems * chunks (the grid is n_work rounded up to a multiple of kXcds)
 };
+
+// Target number of non-empty workgroups of a step launch when the caller leaves the grouping open.
+constexpr int64_t kStepTargetWgs = 4096;
 
 // List validity bound of one atom: 2 |r - ref M| + r_list ||M - I||_F > skin, with
 // M = ref_cell^-1 cell, and M = I exactly when the cell is bitwise unchanged.
@@ -91,7 +98,9 @@ __device__ inline bool list_invalid(const double r[3], const double *ref_pos, in
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st);
 
-int launch_step(int mode, int tl, const StepArgs &a, const PairTable &t, int prec, int64_t n_sys, int64_t max_atoms,
-                hipStream_t st);
+// Fills a.chunks / a.rounds / a.n_work for lanes-per-atom tl and the caller's group size (0: from
+// the batch shape; h_offs are the host system offsets) and launches the step kernel.
+int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &t, int prec, int64_t n_sys,
+                int64_t max_atoms, const int64_t *h_offs, hipStream_t st);
 
 }  // namespace ts

@@ -29,34 +29,39 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   extern __shared__ double lds[];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   constexpr int APB = 256 / TL;
-  const int s = blockIdx.y;
+  const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
+  if (wg >= a.n_work) return;
+  // uniform values: keep them in scalar registers (a vector division result would drag every
+  // address derived from it into vector registers)
+  const int s = __builtin_amdgcn_readfirstlane(wg / a.chunks);
+  const int chunk = __builtin_amdgcn_readfirstlane(wg - s * a.chunks);
   const int64_t a0 = a.offs[s];
   const int ns = (int)(a.offs[s + 1] - a0);
-  const int first = blockIdx.x * APB;
+  const int first = chunk * APB * a.rounds;
   if (first >= ns) return;
   const int tid = threadIdx.x;
   const int grp = tid / TL, lane = tid % TL;
-  const int li = first + grp;
-  const bool own = li < ns;
-  const int64_t i = a0 + li;
   const double *h = a.cell + 9 * (int64_t)s;
 
   if (MODE == kStepFirst) {
     // v += dt/2 a F(r_0); r_1 = r_0 + dt v; list validity of r_1 (cell change included)
-    if (own && lane == 0) {
+    for (int r = 0; r < a.rounds; ++r) {
+      const int li = first + r * APB + grp;
+      if (!(li < ns && lane == 0)) continue;
+      const int64_t i = a0 + li;
       const T *F = static_cast<const T *>(a.force);
       const double sc = a.mass ? a.accel / a.mass[i] : a.accel;
-      double r[3];
+      double rn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double v = fma(a.half_dt * (double)F[c * a.st_vel + i], sc, a.vel[c * a.st_vel + i]);
         a.vel[c * a.st_vel + i] = v;
         const double r0 = a.pos_in[c * a.st_in + i];
         if (a.pos_copy) a.pos_copy[c * a.n_atoms + i] = r0;
-        r[c] = fma(a.dt, v, r0);
-        a.pos_out[c * a.st_out + i] = r[c];
+        rn[c] = fma(a.dt, v, r0);
+        a.pos_out[c * a.st_out + i] = rn[c];
       }
-      if (list_invalid(r, a.ref_pos, a.st_vel, i, h, a.ref_cell + 9 * (int64_t)s, a.skin, a.r_list))
+      if (list_invalid(rn, a.ref_pos, a.st_vel, i, h, a.ref_cell + 9 * (int64_t)s, a.skin, a.r_list))
         flag_system(a, s);
     }
     return;
@@ -73,120 +78,146 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   __syncthreads();
   const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                h22 = h[8];
-  const double rx = own ? lx[li] : 0.0, ry = own ? ly[li] : 0.0, rz = own ? lz[li] : 0.0;
   const uint32_t *__restrict__ nbr = a.nbr;
   const int64_t st = a.st_vel;  // list, reference positions, velocities and forces share the batch stride
-  const int nn = own ? a.n_nbr[i] : 0;
-  const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0 && h00 > 0.0 &&
-                    h11 > 0.0 && h22 > 0.0;
 
   // 3. pair forces of this block's atoms, TL lanes per atom
   constexpr bool EV = MODE == kStepLast || MODE == kStepForceEV;
   constexpr bool FORCE_ONLY = MODE == kStepForce || MODE == kStepForceEV;
-  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-  double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
-  if (own) {
-    const bool single = tab.n_species == 1 || a.species == nullptr;
-    const int si = single ? 0 : a.species[i];
-    const double cut2 = tab.cut2;
-    const int32_t *__restrict__ species = a.species;
-    auto pair = [&](uint32_t ent, const PairCoef &pc, bool check_species) {
-      const int j = entry_j(ent);
-      const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
-      double dx, dy, dz;
-      if (diag) {
-        // off-diagonal products are exact zeros: the same value as the general form below
-        dx = (lx[j] - rx) + S0 * h00;
-        dy = (ly[j] - ry) + S1 * h11;
-        dz = (lz[j] - rz) + S2 * h22;
-      } else {
-        dx = shift_comp(lx[j] - rx, S0, S1, S2, h00, h10, h20);
-        dy = shift_comp(ly[j] - ry, S0, S1, S2, h01, h11, h21);
-        dz = shift_comp(lz[j] - rz, S0, S1, S2, h02, h12, h22);
-      }
-      const double r2 = norm2(dx, dy, dz);
-      if (!(r2 < cut2)) return;
-      const PairCoef &c = check_species ? ltab[si * TS_MAX_SPECIES + species[a0 + j]] : pc;
-      if (KIND == TS_SOFT_SPHERE && !(r2 < c.sig2)) return;
-      const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
-      T phi = (T)0;
-      const T g = pair_g<KIND, T>(c, (T)r2, r2, &phi, EV);
-      const T gx = g * tx, gy = g * ty, gz = g * tz;
-      fx += (double)gx;
-      fy += (double)gy;
-      fz += (double)gz;
-      if (EV) {
-        e += (double)phi;
-        w0 += (double)(gx * tx);
-        w1 += (double)(gy * ty);
-        w2 += (double)(gz * tz);
-        w3 += (double)(gx * ty);
-        w4 += (double)(gx * tz);
-        w5 += (double)(gy * tz);
-      }
-    };
-    if (single) {
-      const PairCoef pc0 = ltab[0];  // loop-invariant coefficients in registers
-      for_row<TL>(nbr, st, i, nn, lane, [&](uint32_t ent) { pair(ent, pc0, false); });
-    } else {
-      for_row<TL>(nbr, st, i, nn, lane, [&](uint32_t ent) { pair(ent, ltab[0], true); });
-    }
-  }
+  double e = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;  // over all rounds
+  for (int r = 0; r < a.rounds; ++r) {
+    const int base = first + r * APB;
+    if (base >= ns) break;  // uniform over the workgroup
+    const int li = base + grp;
+    const bool own = li < ns;
+    const int64_t i = a0 + li;
+    const double rx = own ? lx[li] : 0.0, ry = own ? ly[li] : 0.0, rz = own ? lz[li] : 0.0;
+    const int nn = own ? a.n_nbr[i] : 0;
+    // (evaluated after the atom's own loads: this order keeps the register count of the loop low)
+    const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0 &&
+                      h00 > 0.0 && h11 > 0.0 && h22 > 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (own) {
+      const bool single = tab.n_species == 1 || a.species == nullptr;
+      const int si = single ? 0 : a.species[i];
+      const double cut2 = tab.cut2;
+      const int32_t *__restrict__ species = a.species;
+      // kStepUnroll entries per lane at a time, evaluated without branches (masked by ok and the
+      // cutoff test) so that their LDS loads and float64 chains overlap
+      auto rows = [&](auto diag_c, auto multi_c) {
+        constexpr bool DIAG = decltype(diag_c)::value, MULTI = decltype(multi_c)::value;
+        const PairCoef pc0 = ltab[0];  // loop-invariant coefficients in registers
+        for_row_batched<TL, kStepUnroll>(nbr, st, i, nn, lane, [&](const uint32_t *ent, const bool *ok) {
+          double dx[kStepUnroll], dy[kStepUnroll], dz[kStepUnroll], r2[kStepUnroll];
+          int jj[kStepUnroll];
 #pragma unroll
-  for (int o = 1; o < TL; o <<= 1) {
-    fx += __shfl_xor(fx, o, TL);
-    fy += __shfl_xor(fy, o, TL);
-    fz += __shfl_xor(fz, o, TL);
-  }
-
-  // 4. kicks and drift (lane 0 of each atom)
-  if (own && lane == 0) {
-    T *F = static_cast<T *>(a.force);
-    const T Fx = (T)fx, Fy = (T)fy, Fz = (T)fz;
-    const double sc = FORCE_ONLY ? 0.0 : (a.mass ? a.accel / a.mass[i] : a.accel);
-    const double hx = a.half_dt * (double)Fx, hy = a.half_dt * (double)Fy, hz = a.half_dt * (double)Fz;
-    double vx = 0.0, vy = 0.0, vz = 0.0;
-    if (!FORCE_ONLY) {
-      vx = a.vel[i];
-      vy = a.vel[st + i];
-      vz = a.vel[2 * st + i];
+          for (int u = 0; u < kStepUnroll; ++u) {
+            const int j = entry_j(ent[u]);
+            jj[u] = j;
+            const double S0 = (double)entry_s0(ent[u]), S1 = (double)entry_s1(ent[u]), S2 = (double)entry_s2(ent[u]);
+            if (DIAG) {
+              // off-diagonal products are exact zeros: the same value as the general form below
+              dx[u] = (lx[j] - rx) + S0 * h00;
+              dy[u] = (ly[j] - ry) + S1 * h11;
+              dz[u] = (lz[j] - rz) + S2 * h22;
+            } else {
+              dx[u] = shift_comp(lx[j] - rx, S0, S1, S2, h00, h10, h20);
+              dy[u] = shift_comp(ly[j] - ry, S0, S1, S2, h01, h11, h21);
+              dz[u] = shift_comp(lz[j] - rz, S0, S1, S2, h02, h12, h22);
+            }
+            r2[u] = norm2(dx[u], dy[u], dz[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < kStepUnroll; ++u) {
+            const PairCoef &c = MULTI ? ltab[si * TS_MAX_SPECIES + species[a0 + jj[u]]] : pc0;
+            bool in = ok[u] && r2[u] < cut2;
+            if (KIND == TS_SOFT_SPHERE) in = in && r2[u] < c.sig2;
+            const T tx = (T)dx[u], ty = (T)dy[u], tz = (T)dz[u];
+            T phi = (T)0;
+            T g = pair_g<KIND, T>(c, (T)r2[u], r2[u], &phi, EV);
+            g = in ? g : (T)0;
+            const T gx = g * tx, gy = g * ty, gz = g * tz;
+            fx += (double)gx;
+            fy += (double)gy;
+            fz += (double)gz;
+            if (EV) {
+              e += in ? (double)phi : 0.0;
+              w0 += (double)(gx * tx);
+              w1 += (double)(gy * ty);
+              w2 += (double)(gz * tz);
+              w3 += (double)(gx * ty);
+              w4 += (double)(gx * tz);
+              w5 += (double)(gy * tz);
+            }
+          }
+        });
+      };
+      using yes = std::true_type;
+      using no = std::false_type;
+      if (diag) {
+        if (single) rows(yes{}, no{});
+        else rows(yes{}, yes{});
+      } else {
+        if (single) rows(no{}, no{});
+        else rows(no{}, yes{});
+      }
     }
-    // explicit fused multiply-adds: every kick and drift rounds the same way in every kernel
-    vx = fma(hx, sc, vx);
-    vy = fma(hy, sc, vy);
-    vz = fma(hz, sc, vz);
-    if (FORCE_ONLY) {
-      F[i] = Fx;
-      F[st + i] = Fy;
-      F[2 * st + i] = Fz;
-    } else if (MODE == kStepMid) {
+#pragma unroll
+    for (int o = 1; o < TL; o <<= 1) {
+      fx += __shfl_xor(fx, o, TL);
+      fy += __shfl_xor(fy, o, TL);
+      fz += __shfl_xor(fz, o, TL);
+    }
+
+    // 4. kicks and drift (lane 0 of each atom)
+    if (own && lane == 0) {
+      T *F = static_cast<T *>(a.force);
+      const T Fx = (T)fx, Fy = (T)fy, Fz = (T)fz;
+      const double sc = FORCE_ONLY ? 0.0 : (a.mass ? a.accel / a.mass[i] : a.accel);
+      const double hx = a.half_dt * (double)Fx, hy = a.half_dt * (double)Fy, hz = a.half_dt * (double)Fz;
+      double vx = 0.0, vy = 0.0, vz = 0.0;
+      if (!FORCE_ONLY) {
+        vx = a.vel[i];
+        vy = a.vel[st + i];
+        vz = a.vel[2 * st + i];
+      }
+      // explicit fused multiply-adds: every kick and drift rounds the same way in every kernel
       vx = fma(hx, sc, vx);
       vy = fma(hy, sc, vy);
       vz = fma(hz, sc, vz);
-      const double nx = fma(a.dt, vx, rx), ny = fma(a.dt, vy, ry), nz = fma(a.dt, vz, rz);
-      a.pos_out[i] = nx;
-      a.pos_out[a.st_out + i] = ny;
-      a.pos_out[2 * a.st_out + i] = nz;
-      // the cell is unchanged since the list was built (a changed cell was flagged by the first step)
-      const double dx = nx - a.ref_pos[i], dy = ny - a.ref_pos[st + i], dz = nz - a.ref_pos[2 * st + i];
-      if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list)) flag_system(a, s);
-    } else {
-      F[i] = Fx;
-      F[st + i] = Fy;
-      F[2 * st + i] = Fz;
-      if (a.pos_final) {
-        a.pos_final[i] = rx;
-        a.pos_final[st + i] = ry;
-        a.pos_final[2 * st + i] = rz;
+      if (FORCE_ONLY) {
+        F[i] = Fx;
+        F[st + i] = Fy;
+        F[2 * st + i] = Fz;
+      } else if (MODE == kStepMid) {
+        vx = fma(hx, sc, vx);
+        vy = fma(hy, sc, vy);
+        vz = fma(hz, sc, vz);
+        const double nx = fma(a.dt, vx, rx), ny = fma(a.dt, vy, ry), nz = fma(a.dt, vz, rz);
+        a.pos_out[i] = nx;
+        a.pos_out[a.st_out + i] = ny;
+        a.pos_out[2 * a.st_out + i] = nz;
+        // the cell is unchanged since the list was built (a changed cell was flagged by the first step)
+        const double dx = nx - a.ref_pos[i], dy = ny - a.ref_pos[st + i], dz = nz - a.ref_pos[2 * st + i];
+        if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list)) flag_system(a, s);
+      } else {
+        F[i] = Fx;
+        F[st + i] = Fy;
+        F[2 * st + i] = Fz;
+        if (a.pos_final) {
+          a.pos_final[i] = rx;
+          a.pos_final[st + i] = ry;
+          a.pos_final[2 * st + i] = rz;
+        }
+      }
+      if (!FORCE_ONLY) {
+        a.vel[i] = vx;
+        a.vel[st + i] = vy;
+        a.vel[2 * st + i] = vz;
       }
     }
-    if (!FORCE_ONLY) {
-      a.vel[i] = vx;
-      a.vel[st + i] = vy;
-      a.vel[2 * st + i] = vz;
-    }
-  }
-  if (MODE == kStepMid && blockIdx.x == 0 && tid == 0) {
+  }  // rounds
+  if (MODE == kStepMid && chunk == 0 && tid == 0) {
     a.flag_clear[s] = 0;
     if (s == 0) *a.count_clear = 0;
   }
@@ -273,6 +304,10 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     const double re0 = a.r_list / (vol / sqrt(c0x * c0x + c0y * c0y + c0z * c0z));
     const double re1 = a.r_list / (vol / sqrt(c1x * c1x + c1y * c1y + c1z * c1z));
     const double re2 = a.r_list / (vol / sqrt(c2x * c2x + c2y * c2y + c2z * c2z));
+    // every lattice direction wider than 2 r_list: at most one image of j is within r_list of i,
+    // the nearest one, S = -rint(fractional difference) (a tie at |f + S| = 1/2 is out of reach)
+    const bool wide = re0 < 0.5 - 1e-6 && re1 < 0.5 - 1e-6 && re2 < 0.5 - 1e-6;
+    const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0;
     __syncthreads();
     const int li = c0 + wave;
     if (li >= ns) continue;  // uniform over the wavefront; no block barrier follows before the loop top
@@ -280,7 +315,55 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     const double rx = lx[li], ry = ly[li], rz = lz[li];
     int cnt = 0;
     bool shift_bad = false;
-    for (int j0 = 0; j0 < ns; j0 += kWave) {
+    if (wide) {
+      // one candidate per (i, j): two blocks of 64 candidates per iteration, evaluated without
+      // branches; the pair vector is computed exactly as in the general path below
+      auto scan = [&](auto diag_c) {
+        constexpr bool DIAG = decltype(diag_c)::value;
+        auto cand = [&](int j, uint32_t *e) -> bool {
+          const bool inb = j < ns;
+          const int jc = inb ? j : li;
+          const double drx = lx[jc] - rx, dry = ly[jc] - ry, drz = lz[jc] - rz;
+          double S0, S1, S2;
+          if (DIAG) {
+            S0 = -rint(drx * i00);
+            S1 = -rint(dry * i11);
+            S2 = -rint(drz * i22);
+          } else {
+            S0 = -rint(drx * i00 + dry * i10 + drz * i20);
+            S1 = -rint(drx * i01 + dry * i11 + drz * i21);
+            S2 = -rint(drx * i02 + dry * i12 + drz * i22);
+          }
+          const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+          const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+          const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+          const int s0 = (int)S0, s1 = (int)S1, s2 = (int)S2;
+          const int fs = s0 != 0 ? s0 : (s1 != 0 ? s1 : s2);
+          bool in = inb && norm2(dx, dy, dz) < rl2 && !(jc == li && s0 == 0 && s1 == 0 && s2 == 0) &&
+                    (!a.half || li < jc || (li == jc && fs > 0));
+          if (in && !shift_ok(s0, s1, s2)) {
+            shift_bad = true;
+            in = false;
+          }
+          *e = pack_entry(jc, in ? s0 : 0, in ? s1 : 0, in ? s2 : 0);
+          return in;
+        };
+        for (int j0 = 0; j0 < ns; j0 += 2 * kWave) {
+          uint32_t ea, eb;
+          const bool ca = cand(j0 + lane, &ea), cb = cand(j0 + kWave + lane, &eb);
+          const uint64_t ma = __ballot(ca), mb = __ballot(cb);
+          const int na = __popcll(ma);
+          const int pa = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0));
+          const int pb = cnt + na + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0));
+          if (ca && pa < a.max_nbr) nbr[row_index(pa, i, st)] = ea;
+          if (cb && pb < a.max_nbr) nbr[row_index(pb, i, st)] = eb;
+          cnt += na + __popcll(mb);
+        }
+      };
+      if (diag) scan(std::true_type{});
+      else scan(std::false_type{});
+    }
+    for (int j0 = 0; j0 < (wide ? 0 : ns); j0 += kWave) {
       const int j = j0 + lane;
       int c = 0;
       uint32_t e1 = 0;
@@ -417,10 +500,26 @@ static void launch_step_kt(int tl, int mode, const StepArgs &a, const PairTable 
   }
 }
 
-int launch_step(int mode, int tl, const StepArgs &a, const PairTable &t, int prec, int64_t n_sys, int64_t max_atoms,
-                hipStream_t st) {
+int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &t, int prec, int64_t n_sys,
+                int64_t max_atoms, const int64_t *h_offs, hipStream_t st) {
   const int apb = 256 / tl;
-  const dim3 g((unsigned)ceil_div(max_atoms, apb), (unsigned)n_sys);
+  const int64_t max_rounds = ceil_div(max_atoms, apb);
+  int64_t rounds = 1;
+  if (group_atoms > 0) {
+    rounds = group_atoms / apb;
+  } else {
+    // one round per workgroup until the launch holds about kStepTargetWgs non-empty workgroups
+    int64_t wgs = 0;
+    for (int64_t s = 0; s < n_sys; ++s) wgs += ceil_div(h_offs[s + 1] - h_offs[s], apb);
+    rounds = wgs / kStepTargetWgs;
+  }
+  rounds = rounds < 1 ? 1 : (rounds > max_rounds ? max_rounds : rounds);
+  a.rounds = (int)rounds;
+  a.chunks = (int)ceil_div(max_atoms, apb * rounds);
+  a.n_work = n_sys * a.chunks;
+  const int64_t grid = ceil_div(a.n_work, kXcds) * kXcds;
+  if (grid > 0x7fffffff) return TS_E_CAPACITY;
+  const dim3 g((unsigned)grid);
   const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
   if (prec == TS_PAIR_F32) {
     if (t.kind == TS_LJ) launch_step_kt<TS_LJ, float>(tl, mode, a, t, g, shm, st);

@@ -259,8 +259,8 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
             a.ref_pos[i] = rx;
             a.ref_pos[st + i] = ry;
             a.ref_pos[2 * st + i] = rz;
-            atomicMax((unsigned long long *)&a.status[TS_STATUS_MAX_NBR], (unsigned long long)cnt);
-            if (cnt > a.max_nbr) atomicMax((unsigned long long *)&a.status[TS_STATUS_OVERFLOW], 1ull);
+            status_raise(a.status, TS_STATUS_MAX_NBR, cnt);
+            if (cnt > a.max_nbr) status_raise(a.status, TS_STATUS_OVERFLOW, 1);
           }
         }
         __syncthreads();  // rows are read by other wavefronts below

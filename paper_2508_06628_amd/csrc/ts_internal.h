@@ -314,6 +314,36 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Raise status word k to at least v.  Status words only grow, so the atomic is skipped when a
+// coherent read already shows a value >= v: atomics on one address serialise in L2, and issuing
+// one per atom costs microseconds per thousand atoms.
+__device__ inline void status_raise(int64_t *status, int k, int64_t v) {
+  if (v > __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax((unsigned long long *)&status[k], (unsigned long long)v);
+}
+
+// Workgroup-level status update after a row build: the largest row length and the overflow /
+// image-shift / non-finite flags of all threads go through LDS, then one thread raises the global
+// words.  Must be reached by every thread of the workgroup.
+__device__ inline void block_status(int64_t *status, int cnt, int max_nbr, bool shift_bad, bool nonfinite) {
+  __shared__ int s_max, s_flags;
+  if (threadIdx.x == 0) {
+    s_max = 0;
+    s_flags = 0;
+  }
+  __syncthreads();
+  if (cnt > 0) atomicMax(&s_max, cnt);
+  const int fl = (shift_bad ? 1 : 0) | (nonfinite ? 2 : 0);
+  if (fl) atomicOr(&s_flags, fl);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_max > 0) status_raise(status, TS_STATUS_MAX_NBR, s_max);
+    if (s_max > max_nbr) status_raise(status, TS_STATUS_OVERFLOW, 1);
+    if (s_flags & 1) status_raise(status, TS_STATUS_SHIFT, 1);
+    if (s_flags & 2) status_raise(status, TS_STATUS_NONFINITE, 1);
+  }
+}
+
 // Add the NV per-lane values v[k] into out[s * out_stride + k].  Must be reached by every lane of
 // the wavefront (convergent control flow).  One atomic per value and wavefront when all valid lanes
 // share a system (the common case: systems are contiguous), one per lane otherwise.

@@ -252,10 +252,12 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
                                                  int32_t *__restrict__ n_nbr, int max_nbr, double r_list,
                                                  int half, int64_t *__restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  int cnt = 0;
+  bool shift_bad = false;
+  // no early return: every thread reaches the workgroup-level status update at the end
+  if (i < n && geom[sys_idx[i]].active) {
   const int s = sys_idx[i];
   const NlGeom &g = geom[s];
-  if (!g.active) return;
   const int64_t a0 = offs[s];
   const int64_t base = 2 * a0 + s;
   const double *h = cell + 9 * (int64_t)s;
@@ -282,8 +284,6 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
     hi[0] = hi[1] = hi[2] = -1;
   }
   const double rl2 = r_list * r_list;
-  int cnt = 0;
-  bool shift_bad = false;
   for (int v0 = lo[0]; v0 <= hi[0]; ++v0) {
     const int I0 = floor_div(v0, g.n[0]);
     const int b0 = v0 - I0 * g.n[0];
@@ -337,9 +337,8 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
     nbr[row_index(q + 1, i, stride)] = key;
   }
   n_nbr[i] = nw;
-  atomicMax((unsigned long long *)&status[TS_STATUS_MAX_NBR], (unsigned long long)cnt);
-  if (cnt > max_nbr) atomicMax((unsigned long long *)&status[TS_STATUS_OVERFLOW], 1ull);
-  if (shift_bad) atomicMax((unsigned long long *)&status[TS_STATUS_SHIFT], 1ull);
+  }
+  block_status(status, cnt, max_nbr, shift_bad, false);
 }
 
 // ----------------------------------------------------------------------------- host side

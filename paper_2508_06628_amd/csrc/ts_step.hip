@@ -456,12 +456,11 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
       a.ref_pos[i] = rx;
       a.ref_pos[st + i] = ry;
       a.ref_pos[2 * st + i] = rz;
-      atomicMax((unsigned long long *)&a.status[TS_STATUS_MAX_NBR], (unsigned long long)cnt);
-      if (cnt > a.max_nbr) atomicMax((unsigned long long *)&a.status[TS_STATUS_OVERFLOW], 1ull);
-      if (!(isfinite(rx) && isfinite(ry) && isfinite(rz)))
-        atomicMax((unsigned long long *)&a.status[TS_STATUS_NONFINITE], 1ull);
+      status_raise(a.status, TS_STATUS_MAX_NBR, cnt);
+      if (cnt > a.max_nbr) status_raise(a.status, TS_STATUS_OVERFLOW, 1);
+      if (!(isfinite(rx) && isfinite(ry) && isfinite(rz))) status_raise(a.status, TS_STATUS_NONFINITE, 1);
     }
-    if (__ballot(shift_bad) != 0 && lane == 0) atomicMax((unsigned long long *)&a.status[TS_STATUS_SHIFT], 1ull);
+    if (__ballot(shift_bad) != 0 && lane == 0) status_raise(a.status, TS_STATUS_SHIFT, 1);
   }
 }
 

@@ -33,10 +33,10 @@ __global__ void k_adj_drift(int64_t n, int64_t st, const double *__restrict__ lr
 }
 
 template <int KIND, typename T, bool SINGLE>
-__global__ void __launch_bounds__(256) k_pair_vjp(AdjArgs a, PairTable tab) {
+__global__ void __launch_bounds__(256) k_pair_vjp(PairTable tab, AdjArgs a) {
   __shared__ double acc[TS_MAX_SPECIES * TS_MAX_SPECIES * 3];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
-  if (!SINGLE) table_to_lds(tab, ltab);
+  if (!SINGLE) table_to_lds(ltab);
   if (!SINGLE) {
     for (int k = threadIdx.x; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += blockDim.x) acc[k] = 0.0;
     __syncthreads();
@@ -119,9 +119,9 @@ template <int KIND, typename T>
 static void launch_vjp(const AdjArgs &a, const PairTable &t, bool single, hipStream_t st) {
   const dim3 g((unsigned)ceil_div(a.n, 256));
   if (single)
-    hipLaunchKernelGGL((k_pair_vjp<KIND, T, true>), g, dim3(256), 0, st, a, t);
+    hipLaunchKernelGGL((k_pair_vjp<KIND, T, true>), g, dim3(256), 0, st, t, a);
   else
-    hipLaunchKernelGGL((k_pair_vjp<KIND, T, false>), g, dim3(256), 0, st, a, t);
+    hipLaunchKernelGGL((k_pair_vjp<KIND, T, false>), g, dim3(256), 0, st, t, a);
 }
 
 // ----------------------------------------------------------------------------- RDF

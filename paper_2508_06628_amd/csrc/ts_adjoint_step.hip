@@ -60,7 +60,7 @@ __global__ void k_list_check(StepArgs a, const double *pos, int64_t n) {
 }
 
 template <int KIND, typename T, int TL, bool SINGLE>
-__global__ void __launch_bounds__(256) k_adj_step(AdjStepArgs a, PairTable tab) {
+__global__ void __launch_bounds__(256) k_adj_step(PairTable tab, AdjStepArgs a) {
   extern __shared__ double lds[];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   __shared__ double acc[TS_MAX_SPECIES * TS_MAX_SPECIES * 3];
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) k_adj_step(AdjStepArgs a, PairTable tab) 
   const int li = first + grp;
   const bool own = li < ns;
   const int64_t i = a0 + li;
-  table_to_lds(tab, ltab);
+  table_to_lds(ltab);
   for (int k = tid; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += 256) acc[k] = 0.0;
   // stage r_n and the drifted u of the whole system
   double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
@@ -197,9 +197,9 @@ __global__ void k_copy3(int64_t n, const double *src, int64_t st_src, double *ds
 template <int KIND, typename T, int TL>
 static void launch_adj_k(bool single, dim3 g, size_t shm, const AdjStepArgs &a, const PairTable &t, hipStream_t st) {
   if (single)
-    hipLaunchKernelGGL((k_adj_step<KIND, T, TL, true>), g, dim3(256), shm, st, a, t);
+    hipLaunchKernelGGL((k_adj_step<KIND, T, TL, true>), g, dim3(256), shm, st, t, a);
   else
-    hipLaunchKernelGGL((k_adj_step<KIND, T, TL, false>), g, dim3(256), shm, st, a, t);
+    hipLaunchKernelGGL((k_adj_step<KIND, T, TL, false>), g, dim3(256), shm, st, t, a);
 }
 
 template <int KIND, typename T>

@@ -67,7 +67,7 @@ __device__ inline void inv3p(const double *h, double *inv) {
 }
 
 template <int KIND, typename T, bool CELL>
-__global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable tab) {
+__global__ void __launch_bounds__(kPT) k_fire_persistent(PairTable tab, FirePArgs a) {
   extern __shared__ double lds[];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   __shared__ double red[kPW * kPR];
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
   __shared__ double sh[64];
   __shared__ int s_sys;
   __shared__ int s_any;
-  table_to_lds(tab, ltab);
+  table_to_lds(ltab);
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const ts_fire_config &cf = a.f.cfg;
   const int64_t st = a.f.stride;
@@ -275,6 +275,7 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
       double q[kPR];
 #pragma unroll
       for (int k = 0; k < kPR; ++k) q[k] = 0.0;
+      double wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // sum g d (x) d: xx yy zz xy xz yz
       T *F = static_cast<T *>(a.f.force);
       for (int li0 = 0; li0 < ns; li0 += G) {
         const int li = li0 + grp;
@@ -296,20 +297,11 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
             if (!(r2 < tab.cut2)) continue;
             const PairCoef &pc = ltab[single ? 0 : si * TS_MAX_SPECIES + a.species[a0 + j]];
             if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
-            const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
             T phi = (T)0;
-            const T g = pair_g<KIND, T>(pc, (T)r2, r2, &phi, true);
-            const T gx = g * tx, gy = g * ty, gz = g * tz;
-            fx += (double)gx;
-            fy += (double)gy;
-            fz += (double)gz;
+            const double g = (double)pair_g<KIND, T>(pc, (T)r2, r2, &phi, true);
+            acc_force(g, dx, dy, dz, fx, fy, fz);
             q[4] += 0.5 * (double)phi;
-            q[5] -= 0.5 * (double)(gx * tx);
-            q[6] -= 0.5 * (double)(gx * ty);
-            q[7] -= 0.5 * (double)(gx * tz);
-            q[9] -= 0.5 * (double)(gy * ty);
-            q[10] -= 0.5 * (double)(gy * tz);
-            q[13] -= 0.5 * (double)(gz * tz);
+            acc_virial(g, dx, dy, dz, wv);
           }
         }
         for (int o = 1; o < tl; o <<= 1) {
@@ -336,6 +328,13 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
           q[3] += g0 * g0 + g1 * g1 + g2 * g2;
         }
       }
+      // virial W = -1/2 sum over ordered pairs g d (x) d (slots xx xy xz . yy yz . . zz)
+      q[5] = -0.5 * wv[0];
+      q[6] = -0.5 * wv[3];
+      q[7] = -0.5 * wv[4];
+      q[9] = -0.5 * wv[1];
+      q[10] = -0.5 * wv[5];
+      q[13] = -0.5 * wv[2];
       // block reduction in a fixed order
 #pragma unroll
       for (int k = 0; k < kPR; ++k) {
@@ -493,9 +492,9 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(FirePArgs a, PairTable 
 template <int KIND, typename T>
 static void launch_fp_kt(bool cell, dim3 g, size_t shm, const FirePArgs &a, const PairTable &t, hipStream_t st) {
   if (cell)
-    hipLaunchKernelGGL((k_fire_persistent<KIND, T, true>), g, dim3(kPT), shm, st, a, t);
+    hipLaunchKernelGGL((k_fire_persistent<KIND, T, true>), g, dim3(kPT), shm, st, t, a);
   else
-    hipLaunchKernelGGL((k_fire_persistent<KIND, T, false>), g, dim3(kPT), shm, st, a, t);
+    hipLaunchKernelGGL((k_fire_persistent<KIND, T, false>), g, dim3(kPT), shm, st, t, a);
 }
 
 int fire_persistent(const ts_batch *b, const ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,

@@ -12,16 +12,16 @@
 namespace ts {
 
 template <int KIND, typename T, bool EV, bool SINGLE>
-__global__ void __launch_bounds__(256) k_pair_forces(ForceArgs a, PairTable tab) {
+__global__ void __launch_bounds__(256) k_pair_forces(PairTable tab, ForceArgs a) {
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
-  if (!SINGLE) table_to_lds(tab, ltab);
+  if (!SINGLE) table_to_lds(ltab);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = i < a.n;
   const int64_t ii = valid ? i : 0;
   const int s = valid ? a.sys_idx[ii] : 0;
   if (valid && a.skip && a.skip[s]) valid = false;
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-  double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;  // xx yy zz xy xz yz
+  double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // xx yy zz xy xz yz
   if (valid) {
     const int64_t st = a.stride;
     const int64_t a0 = a.offs[s];
@@ -44,21 +44,12 @@ __global__ void __launch_bounds__(256) k_pair_forces(ForceArgs a, PairTable tab)
       if (!(r2 < cut2)) continue;
       const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : ltab[si * TS_MAX_SPECIES + a.species[j]];
       if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
-      const T tx = (T)dx, ty = (T)dy, tz = (T)dz;
       T phi = (T)0;
-      const T g = pair_g<KIND, T>(pc, (T)r2, r2, &phi, EV);
-      const T gx = g * tx, gy = g * ty, gz = g * tz;
-      fx += (double)gx;
-      fy += (double)gy;
-      fz += (double)gz;
+      const double g = (double)pair_g<KIND, T>(pc, (T)r2, r2, &phi, EV);
+      acc_force(g, dx, dy, dz, fx, fy, fz);
       if (EV) {
         e += (double)phi;
-        w0 += (double)(gx * tx);
-        w1 += (double)(gy * ty);
-        w2 += (double)(gz * tz);
-        w3 += (double)(gx * ty);
-        w4 += (double)(gx * tz);
-        w5 += (double)(gy * tz);
+        acc_virial(g, dx, dy, dz, w);
       }
     }
     T *F = static_cast<T *>(a.force);
@@ -72,8 +63,8 @@ __global__ void __launch_bounds__(256) k_pair_forces(ForceArgs a, PairTable tab)
       add_by_system<1>(a.energy, 1, s, valid, ev);
     }
     if (a.virial) {
-      const double wv[9] = {-0.5 * w0, -0.5 * w3, -0.5 * w4, -0.5 * w3, -0.5 * w1,
-                            -0.5 * w5, -0.5 * w4, -0.5 * w5, -0.5 * w2};
+      const double wv[9] = {-0.5 * w[0], -0.5 * w[3], -0.5 * w[4], -0.5 * w[3], -0.5 * w[1],
+                            -0.5 * w[5], -0.5 * w[4], -0.5 * w[5], -0.5 * w[2]};
       add_by_system<9>(a.virial, 9, s, valid, wv);
     }
   }
@@ -92,14 +83,14 @@ template <int KIND, typename T>
 static void launch_kt(const ForceArgs &a, const PairTable &t, bool ev, bool single, dim3 g, hipStream_t st) {
   if (ev) {
     if (single)
-      hipLaunchKernelGGL((k_pair_forces<KIND, T, true, true>), g, dim3(256), 0, st, a, t);
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, true, true>), g, dim3(256), 0, st, t, a);
     else
-      hipLaunchKernelGGL((k_pair_forces<KIND, T, true, false>), g, dim3(256), 0, st, a, t);
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, true, false>), g, dim3(256), 0, st, t, a);
   } else {
     if (single)
-      hipLaunchKernelGGL((k_pair_forces<KIND, T, false, true>), g, dim3(256), 0, st, a, t);
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, false, true>), g, dim3(256), 0, st, t, a);
     else
-      hipLaunchKernelGGL((k_pair_forces<KIND, T, false, false>), g, dim3(256), 0, st, a, t);
+      hipLaunchKernelGGL((k_pair_forces<KIND, T, false, false>), g, dim3(256), 0, st, t, a);
   }
 }
 

@@ -54,6 +54,14 @@ __host__ __device__ inline uint32_t pack_entry(int j_local, int s0, int s1, int 
   return ((uint32_t)j_local << 15) | ((uint32_t)(s0 + 16) << 10) | ((uint32_t)(s1 + 16) << 5) | (uint32_t)(s2 + 16);
 }
 __device__ inline int entry_j(uint32_t e) { return (int)(e >> 15); }
+// The image shifts as exact doubles without a conversion instruction: for a field value u < 2^20
+// the bit pattern 0x43300000:u is the double 2^52 + u, so S = u - 16 = that - (2^52 + 16).
+__device__ inline double entry_sd(uint32_t field) {
+  return __hiloint2double(0x43300000, (int)field) - 4503599627370512.0;
+}
+__device__ inline double entry_s0d(uint32_t e) { return entry_sd((e >> 10) & 31u); }
+__device__ inline double entry_s1d(uint32_t e) { return entry_sd((e >> 5) & 31u); }
+__device__ inline double entry_s2d(uint32_t e) { return entry_sd(e & 31u); }
 __device__ inline int entry_s0(uint32_t e) { return (int)((e >> 10) & 31u) - 16; }
 __device__ inline int entry_s1(uint32_t e) { return (int)((e >> 5) & 31u) - 16; }
 __device__ inline int entry_s2(uint32_t e) { return (int)(e & 31u) - 16; }
@@ -136,14 +144,14 @@ __device__ inline void for_row(const uint32_t *__restrict__ nbr, int64_t st, int
 // in u order to sum like the plain loop.
 template <int TL, int U, typename F>
 __device__ inline void for_row_batched(const uint32_t *__restrict__ nbr, int64_t st, int64_t i, int nn, int lane,
-                                       F &&f) {
+                                       F &&f, int k_begin = 0) {
   uint32_t cur[U], nxt[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int kk = lane + u * TL;
+    const int kk = k_begin + lane + u * TL;
     cur[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
   }
-  for (int k = lane; k < nn; k += U * TL) {
+  for (int k = k_begin + lane; k < nn; k += U * TL) {
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -157,13 +165,55 @@ __device__ inline void for_row_batched(const uint32_t *__restrict__ nbr, int64_t
   }
 }
 
-// Copy the species-pair table into LDS using static indices only: indexing a by-value kernel
-// argument with a run-time index makes the compiler keep a private (scratch) copy per lane.
-// Must be reached by every thread of the workgroup.
-__device__ inline void table_to_lds(const PairTable &t, PairCoef *dst) {
+// As for_row_batched, but R entries of the lane (k = kc + lane + m TL, m < R) are loaded into
+// registers before any is used, so their global loads are in flight together: a kernel starts
+// with a cold L2, and a load issued one visit ahead waits for the far cache every time.  Rows
+// longer than R TL take further chunks of R.  The trip counts follow the longest row of the
+// wavefront (uniform control flow; shorter rows are masked by ok).  Same visiting order.
+// Must be reached by every lane of the wavefront.
+// i must be a valid row (any row of the list for lanes without an atom, which pass nn = 0) and cap
+// the row capacity: loads past the end of a row read entries of the row's capacity that the
+// visit then masks out, so the loads need no branches.
+template <int TL, int U, int R, typename F>
+__device__ inline void for_row_regs(const uint32_t *__restrict__ nbr, int64_t st, int64_t i, int nn, int cap,
+                                    int lane, F &&f) {
+  static_assert(R % U == 0, "R must be a multiple of U");
+  int nmax = nn;
 #pragma unroll
-  for (int k = 0; k < TS_MAX_SPECIES * TS_MAX_SPECIES; ++k)
-    if ((int)threadIdx.x == k) dst[k] = t.c[k];
+  for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
+  nmax = __builtin_amdgcn_readfirstlane(nmax);
+  for (int kc = 0; kc < nmax; kc += R * TL) {
+    uint32_t ent[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int k = kc + lane + m * TL;
+      ent[m] = nbr[row_index(k < cap ? k : cap - 1, i, st)];
+    }
+    // pin the loaded values here: without this the compiler sinks each load next to its first use
+    // (one far-cache round trip per batch instead of one for all R)
+#pragma unroll
+    for (int m = 0; m < R; ++m) asm volatile("" : "+v"(ent[m]));
+#pragma unroll
+    for (int m0 = 0; m0 < R; m0 += U) {
+      if (kc + m0 * TL >= nmax) break;  // uniform
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) ok[u] = kc + lane + (m0 + u) * TL < nn;
+      f(&ent[m0], ok);
+      // keep the batches apart: evaluating later batches' decodes early would keep them all live
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Copy the species-pair table into LDS.  Every kernel that takes a PairTable takes it as its FIRST
+// argument, so the table's kernarg copy starts at the kernarg segment base; reading it through that
+// pointer allows a run-time index (one lane per entry, all loads issued together), whereas a
+// by-value parameter indexed at run time gets a private per-lane copy and a static-index loop
+// issues one dependent kernarg load per entry.  Must be reached by every thread of the workgroup.
+__device__ inline void table_to_lds(PairCoef *dst) {
+  const PairTable *t = (const PairTable *)__builtin_amdgcn_kernarg_segment_ptr();
+  if (threadIdx.x < TS_MAX_SPECIES * TS_MAX_SPECIES) dst[threadIdx.x] = t->c[threadIdx.x];
   __syncthreads();
 }
 
@@ -220,6 +270,25 @@ __device__ inline double pair_g<TS_SOFT_SPHERE, double>(const PairCoef &pc, doub
   const double u = 1.0 - r * pc.c;
   if (want_phi) *phi = 0.5 * pc.a * u * u;
   return -pc.a * pc.c * u / r;
+}
+
+// One pair's contribution to atom i: g = phi'(r)/r comes from the pair function (pair precision);
+// it multiplies the float64 pair vector d = r_j - r_i + S h in float64 and the force sums in
+// float64 (F_i += g d).  The virial variant also accumulates the six distinct entries of
+// sum g d (x) d (xx yy zz xy xz yz).  Every force kernel uses these, so they agree bitwise.
+__device__ inline void acc_force(double g, double dx, double dy, double dz, double &fx, double &fy, double &fz) {
+  fx = fma(g, dx, fx);
+  fy = fma(g, dy, fy);
+  fz = fma(g, dz, fz);
+}
+__device__ inline void acc_virial(double g, double dx, double dy, double dz, double (&w)[6]) {
+  const double gx = g * dx, gy = g * dy, gz = g * dz;
+  w[0] = fma(gx, dx, w[0]);
+  w[1] = fma(gy, dy, w[1]);
+  w[2] = fma(gz, dz, w[2]);
+  w[3] = fma(gx, dy, w[3]);
+  w[4] = fma(gx, dz, w[4]);
+  w[5] = fma(gy, dz, w[5]);
 }
 
 // Second-derivative data for the adjoint: returns g = phi'/r and h = phi''(r); all in T.

@@ -10,7 +10,9 @@ constexpr int kStepMid = 1;    // forces, two half kicks, drift, validity test
 constexpr int kStepLast = 2;   // forces (+ energy, virial), last half kick
 constexpr int kStepForce = 3;  // forces only (ts_pair_forces)
 constexpr int kStepForceEV = 4;  // forces, energy and virial (ts_pair_forces)
+constexpr int kStepThreads = 256;  // workgroup size of the step kernel
 constexpr int kStepUnroll = 4;      // row entries a lane evaluates together in the step kernel
+constexpr int kStepRegEntries = 8; // row entries per lane loaded into registers up front
 constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)
 
 struct StepArgs {

@@ -6,9 +6,9 @@
 //   wavefront builds the row of one atom: its 64 lanes test 64 candidate atoms at a time under every
 //   lattice image in reach, and the per-lane counts are combined with a wavefront prefix sum, so
 //   the row comes out in the canonical (j, S0, S1, S2) order without a sort.
-// k_step (step n): a workgroup owns APB = 256/TL atoms of one system (TL lanes per atom); it stages
-//   the system's positions r_n in LDS, evaluates the pair forces of its atoms (TL lanes per atom,
-//   reduced across lanes), applies the two half kicks that meet at step n and the drift to r_{n+1}
+// k_step (step n): a workgroup owns `rounds` groups of APB = kStepThreads/TL consecutive atoms of
+//   one system (TL lanes per atom); it stages the system's positions r_n in LDS once, evaluates the
+//   pair forces of its atoms (TL lanes per atom, reduced across lanes), applies the two half kicks that meet at step n and the drift to r_{n+1}
 //   (written to the other position buffer) and tests the list validity bound for r_{n+1}, appending
 //   the system to the next rebuild list when it is exceeded.
 // Systems never exchange data, so no synchronisation between workgroups is needed beyond the
@@ -25,10 +25,10 @@ __device__ inline void flag_system(const StepArgs &a, int s) {
 }
 
 template <int KIND, typename T, int TL, int MODE>
-__global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
+__global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a) {
   extern __shared__ double lds[];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
-  constexpr int APB = 256 / TL;
+  constexpr int APB = kStepThreads / TL;
   const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
   if (wg >= a.n_work) return;
   // uniform values: keep them in scalar registers (a vector division result would drag every
@@ -67,10 +67,11 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
     return;
   }
 
-  table_to_lds(tab, ltab);
+  const bool single = tab.n_species == 1 || a.species == nullptr;  // uniform
+  if (!single) table_to_lds(ltab);
   // 1. stage r_n of the whole system
   double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
-  for (int k = tid; k < ns; k += 256) {
+  for (int k = tid; k < ns; k += kStepThreads) {
     lx[k] = a.pos_in[a0 + k];
     ly[k] = a.pos_in[a.st_in + a0 + k];
     lz[k] = a.pos_in[2 * a.st_in + a0 + k];
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   // 3. pair forces of this block's atoms, TL lanes per atom
   constexpr bool EV = MODE == kStepLast || MODE == kStepForceEV;
   constexpr bool FORCE_ONLY = MODE == kStepForce || MODE == kStepForceEV;
-  double e = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;  // over all rounds
+  double e = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // over all rounds
   for (int r = 0; r < a.rounds; ++r) {
     const int base = first + r * APB;
     if (base >= ns) break;  // uniform over the workgroup
@@ -97,33 +98,43 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
     const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0 &&
                       h00 > 0.0 && h11 > 0.0 && h22 > 0.0;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (own) {
-      const bool single = tab.n_species == 1 || a.species == nullptr;
-      const int si = single ? 0 : a.species[i];
+    {
+      // every lane takes part (the row visit is wavefront-wide); lanes without an atom visit the
+      // row of the system's first atom with nn = 0, which masks every entry out
+      const int64_t irow = own ? i : a0;
+      const int si = (single || !own) ? 0 : a.species[i];
       const double cut2 = tab.cut2;
       const int32_t *__restrict__ species = a.species;
       // kStepUnroll entries per lane at a time, evaluated without branches (masked by ok and the
       // cutoff test) so that their LDS loads and float64 chains overlap
       auto rows = [&](auto diag_c, auto multi_c) {
         constexpr bool DIAG = decltype(diag_c)::value, MULTI = decltype(multi_c)::value;
-        const PairCoef pc0 = ltab[0];  // loop-invariant coefficients in registers
-        for_row_batched<TL, kStepUnroll>(nbr, st, i, nn, lane, [&](const uint32_t *ent, const bool *ok) {
+        const PairCoef pc0 = tab.c[0];  // loop-invariant coefficients in registers
+        for_row_regs<TL, kStepUnroll, kStepRegEntries>(nbr, st, irow, nn, a.max_nbr, lane,
+                                                       [&](const uint32_t *ent, const bool *ok) {
           double dx[kStepUnroll], dy[kStepUnroll], dz[kStepUnroll], r2[kStepUnroll];
           int jj[kStepUnroll];
+          // all LDS reads first, then the shift vectors (independent of them), then the pair vectors
 #pragma unroll
           for (int u = 0; u < kStepUnroll; ++u) {
-            const int j = entry_j(ent[u]);
+            const int j = ok[u] ? entry_j(ent[u]) : 0;  // masked visits read a staged atom
             jj[u] = j;
-            const double S0 = (double)entry_s0(ent[u]), S1 = (double)entry_s1(ent[u]), S2 = (double)entry_s2(ent[u]);
+            dx[u] = lx[j];
+            dy[u] = ly[j];
+            dz[u] = lz[j];
+          }
+#pragma unroll
+          for (int u = 0; u < kStepUnroll; ++u) {
+            const double S0 = entry_s0d(ent[u]), S1 = entry_s1d(ent[u]), S2 = entry_s2d(ent[u]);
             if (DIAG) {
-              // off-diagonal products are exact zeros: the same value as the general form below
-              dx[u] = (lx[j] - rx) + S0 * h00;
-              dy[u] = (ly[j] - ry) + S1 * h11;
-              dz[u] = (lz[j] - rz) + S2 * h22;
+              // off-diagonal products are exact zeros: the same value as the general form
+              dx[u] = (dx[u] - rx) + S0 * h00;
+              dy[u] = (dy[u] - ry) + S1 * h11;
+              dz[u] = (dz[u] - rz) + S2 * h22;
             } else {
-              dx[u] = shift_comp(lx[j] - rx, S0, S1, S2, h00, h10, h20);
-              dy[u] = shift_comp(ly[j] - ry, S0, S1, S2, h01, h11, h21);
-              dz[u] = shift_comp(lz[j] - rz, S0, S1, S2, h02, h12, h22);
+              dx[u] = shift_comp(dx[u] - rx, S0, S1, S2, h00, h10, h20);
+              dy[u] = shift_comp(dy[u] - ry, S0, S1, S2, h01, h11, h21);
+              dz[u] = shift_comp(dz[u] - rz, S0, S1, S2, h02, h12, h22);
             }
             r2[u] = norm2(dx[u], dy[u], dz[u]);
           }
@@ -132,22 +143,13 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
             const PairCoef &c = MULTI ? ltab[si * TS_MAX_SPECIES + species[a0 + jj[u]]] : pc0;
             bool in = ok[u] && r2[u] < cut2;
             if (KIND == TS_SOFT_SPHERE) in = in && r2[u] < c.sig2;
-            const T tx = (T)dx[u], ty = (T)dy[u], tz = (T)dz[u];
             T phi = (T)0;
-            T g = pair_g<KIND, T>(c, (T)r2[u], r2[u], &phi, EV);
-            g = in ? g : (T)0;
-            const T gx = g * tx, gy = g * ty, gz = g * tz;
-            fx += (double)gx;
-            fy += (double)gy;
-            fz += (double)gz;
+            const T gt = pair_g<KIND, T>(c, (T)r2[u], r2[u], &phi, EV);
+            const double g = in ? (double)gt : 0.0;
+            acc_force(g, dx[u], dy[u], dz[u], fx, fy, fz);
             if (EV) {
               e += in ? (double)phi : 0.0;
-              w0 += (double)(gx * tx);
-              w1 += (double)(gy * ty);
-              w2 += (double)(gz * tz);
-              w3 += (double)(gx * ty);
-              w4 += (double)(gx * tz);
-              w5 += (double)(gy * tz);
+              acc_virial(g, dx[u], dy[u], dz[u], w);
             }
           }
         });
@@ -224,8 +226,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
   if (EV && (a.epot || a.virial)) {
     // every lane of the block belongs to system s
     const double ev = wave_sum(0.5 * e);
-    const double v0 = wave_sum(-0.5 * w0), v1 = wave_sum(-0.5 * w1), v2 = wave_sum(-0.5 * w2);
-    const double v3 = wave_sum(-0.5 * w3), v4 = wave_sum(-0.5 * w4), v5 = wave_sum(-0.5 * w5);
+    const double v0 = wave_sum(-0.5 * w[0]), v1 = wave_sum(-0.5 * w[1]), v2 = wave_sum(-0.5 * w[2]);
+    const double v3 = wave_sum(-0.5 * w[3]), v4 = wave_sum(-0.5 * w[4]), v5 = wave_sum(-0.5 * w[5]);
     if ((tid % kWave) == 0) {
       if (a.epot) atomicAdd(&a.epot[s], ev);
       if (a.virial) {
@@ -247,6 +249,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a, PairTable tab) {
 // Rebuild rows: one wavefront per atom; a workgroup of kRebuildWaves wavefronts handles that many
 // consecutive atoms of one flagged system ("chunks"; chunks_per_sys covers the largest system).
 constexpr int kRebuildWaves = 8;
+constexpr int kRebuildBlocks = 4;  // candidate blocks of 64 one wavefront tests together
 
 // Candidate images of one (i, j) pair along one lattice direction: integers S with
 // |ds + S| < reach (+ a rounding margin), ds the fractional difference.
@@ -324,20 +327,25 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
           const bool inb = j < ns;
           const int jc = inb ? j : li;
           const double drx = lx[jc] - rx, dry = ly[jc] - ry, drz = lz[jc] - rz;
-          double S0, S1, S2;
+          double f0, f1, f2;
           if (DIAG) {
-            S0 = -rint(drx * i00);
-            S1 = -rint(dry * i11);
-            S2 = -rint(drz * i22);
+            f0 = drx * i00;
+            f1 = dry * i11;
+            f2 = drz * i22;
           } else {
-            S0 = -rint(drx * i00 + dry * i10 + drz * i20);
-            S1 = -rint(drx * i01 + dry * i11 + drz * i21);
-            S2 = -rint(drx * i02 + dry * i12 + drz * i22);
+            f0 = drx * i00 + dry * i10 + drz * i20;
+            f1 = drx * i01 + dry * i11 + drz * i21;
+            f2 = drx * i02 + dry * i12 + drz * i22;
           }
+          // nearest integers without rounding or conversion instructions: t = f + 1.5 2^52 rounds
+          // f to an integer n (ties to even, like rint) for |f| < 2^51, and the low word of t is n
+          constexpr double kRound = 6755399441055744.0;
+          const double t0 = f0 + kRound, t1 = f1 + kRound, t2 = f2 + kRound;
+          const double S0 = kRound - t0, S1 = kRound - t1, S2 = kRound - t2;  // -rint(f), exact
+          const int s0 = -__double2loint(t0), s1 = -__double2loint(t1), s2 = -__double2loint(t2);
           const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
           const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
           const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
-          const int s0 = (int)S0, s1 = (int)S1, s2 = (int)S2;
           const int fs = s0 != 0 ? s0 : (s1 != 0 ? s1 : s2);
           bool in = inb && norm2(dx, dy, dz) < rl2 && !(jc == li && s0 == 0 && s1 == 0 && s2 == 0) &&
                     (!a.half || li < jc || (li == jc && fs > 0));
@@ -348,17 +356,26 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
           *e = pack_entry(jc, in ? s0 : 0, in ? s1 : 0, in ? s2 : 0);
           return in;
         };
-        for (int j0 = 0; j0 < ns; j0 += 2 * kWave) {
-          uint32_t ea, eb;
-          const bool ca = cand(j0 + lane, &ea), cb = cand(j0 + kWave + lane, &eb);
-          const uint64_t ma = __ballot(ca), mb = __ballot(cb);
-          const int na = __popcll(ma);
-          const int pa = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0));
-          const int pb = cnt + na + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0));
-          if (ca && pa < a.max_nbr) nbr[row_index(pa, i, st)] = ea;
-          if (cb && pb < a.max_nbr) nbr[row_index(pb, i, st)] = eb;
-          cnt += na + __popcll(mb);
-        }
+        // KB blocks of 64 candidates: all KB tests first (independent chains), then the
+        // compaction of each block in j order
+        auto blocks = [&](int j0, auto kb_c) {
+          constexpr int KB = decltype(kb_c)::value;
+          uint32_t e[KB];
+          bool c[KB];
+#pragma unroll
+          for (int b = 0; b < KB; ++b) c[b] = cand(j0 + b * kWave + lane, &e[b]);
+#pragma unroll
+          for (int b = 0; b < KB; ++b) {
+            const uint64_t m = __ballot(c[b]);
+            const int p = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+            if (c[b] && p < a.max_nbr) nbr[row_index(p, i, st)] = e[b];
+            cnt += __popcll(m);
+          }
+        };
+        int j0 = 0;
+        for (; j0 + kRebuildBlocks * kWave <= ns; j0 += kRebuildBlocks * kWave)
+          blocks(j0, std::integral_constant<int, kRebuildBlocks>{});
+        for (; j0 < ns; j0 += kWave) blocks(j0, std::integral_constant<int, 1>{});
       };
       if (diag) scan(std::true_type{});
       else scan(std::false_type{});
@@ -477,15 +494,15 @@ int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStrea
 template <int KIND, typename T, int TL>
 static void launch_step_k(int mode, const StepArgs &a, const PairTable &t, dim3 g, size_t shm, hipStream_t st) {
   if (mode == kStepFirst)
-    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepFirst>), g, dim3(256), 0, st, a, t);
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepFirst>), g, dim3(kStepThreads), 0, st, t, a);
   else if (mode == kStepMid)
-    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepMid>), g, dim3(256), shm, st, a, t);
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepMid>), g, dim3(kStepThreads), shm, st, t, a);
   else if (mode == kStepLast)
-    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLast>), g, dim3(256), shm, st, a, t);
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLast>), g, dim3(kStepThreads), shm, st, t, a);
   else if (mode == kStepForce)
-    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepForce>), g, dim3(256), shm, st, a, t);
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepForce>), g, dim3(kStepThreads), shm, st, t, a);
   else
-    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepForceEV>), g, dim3(256), shm, st, a, t);
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepForceEV>), g, dim3(kStepThreads), shm, st, t, a);
 }
 
 template <int KIND, typename T>
@@ -501,7 +518,7 @@ static void launch_step_kt(int tl, int mode, const StepArgs &a, const PairTable 
 
 int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &t, int prec, int64_t n_sys,
                 int64_t max_atoms, const int64_t *h_offs, hipStream_t st) {
-  const int apb = 256 / tl;
+  const int apb = kStepThreads / tl;
   const int64_t max_rounds = ceil_div(max_atoms, apb);
   int64_t rounds = 1;
   if (group_atoms > 0) {

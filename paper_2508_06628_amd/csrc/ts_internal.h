@@ -165,47 +165,6 @@ __device__ inline void for_row_batched(const uint32_t *__restrict__ nbr, int64_t
   }
 }
 
-// As for_row_batched, but R entries of the lane (k = kc + lane + m TL, m < R) are loaded into
-// registers before any is used, so their global loads are in flight together: a kernel starts
-// with a cold L2, and a load issued one visit ahead waits for the far cache every time.  Rows
-// longer than R TL take further chunks of R.  The trip counts follow the longest row of the
-// wavefront (uniform control flow; shorter rows are masked by ok).  Same visiting order.
-// Must be reached by every lane of the wavefront.
-// i must be a valid row (any row of the list for lanes without an atom, which pass nn = 0) and cap
-// the row capacity: loads past the end of a row read entries of the row's capacity that the
-// visit then masks out, so the loads need no branches.
-template <int TL, int U, int R, typename F>
-__device__ inline void for_row_regs(const uint32_t *__restrict__ nbr, int64_t st, int64_t i, int nn, int cap,
-                                    int lane, F &&f) {
-  static_assert(R % U == 0, "R must be a multiple of U");
-  int nmax = nn;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
-  nmax = __builtin_amdgcn_readfirstlane(nmax);
-  for (int kc = 0; kc < nmax; kc += R * TL) {
-    uint32_t ent[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const int k = kc + lane + m * TL;
-      ent[m] = nbr[row_index(k < cap ? k : cap - 1, i, st)];
-    }
-    // pin the loaded values here: without this the compiler sinks each load next to its first use
-    // (one far-cache round trip per batch instead of one for all R)
-#pragma unroll
-    for (int m = 0; m < R; ++m) asm volatile("" : "+v"(ent[m]));
-#pragma unroll
-    for (int m0 = 0; m0 < R; m0 += U) {
-      if (kc + m0 * TL >= nmax) break;  // uniform
-      bool ok[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) ok[u] = kc + lane + (m0 + u) * TL < nn;
-      f(&ent[m0], ok);
-      // keep the batches apart: evaluating later batches' decodes early would keep them all live
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-}
-
 // Copy the species-pair table into LDS.  Every kernel that takes a PairTable takes it as its FIRST
 // argument, so the table's kernarg copy starts at the kernarg segment base; reading it through that
 // pointer allows a run-time index (one lane per entry, all loads issued together), whereas a

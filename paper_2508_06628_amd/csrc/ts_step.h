@@ -12,7 +12,6 @@ constexpr int kStepForce = 3;  // forces only (ts_pair_forces)
 constexpr int kStepForceEV = 4;  // forces, energy and virial (ts_pair_forces)
 constexpr int kStepThreads = 256;  // workgroup size of the step kernel
 constexpr int kStepUnroll = 4;      // row entries a lane evaluates together in the step kernel
-constexpr int kStepRegEntries = 8; // row entries per lane loaded into registers up front
 constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)
 
 struct StepArgs {
@@ -46,6 +45,7 @@ struct StepArgs {
   int chunks;      // workgroups per system; each owns rounds * 256/TL consecutive atoms
   int rounds;
   int64_t n_work;  // n_systems * chunks (the grid is n_work rounded up to a multiple of kXcds)
+  int n_sys;       // systems in the batch (rebuild launch)
 };
 
 // Target number of non-empty workgroups of a step launch when the caller leaves the grouping open.

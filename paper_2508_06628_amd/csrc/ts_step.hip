@@ -19,8 +19,11 @@
 
 namespace ts {
 
-// Flag system s for a rebuild before the next step, appending it once to that step's list.
+// Flag system s for a rebuild before the next step, appending it once to that step's list.  Many
+// atoms of a system cross the bound in the same step; a plain read skips the exchange once the flag
+// is visibly set (same-address atomics serialise), and the exchange still decides who appends.
 __device__ inline void flag_system(const StepArgs &a, int s) {
+  if (__hip_atomic_load(&a.flag_next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   if (atomicExch(&a.flag_next[s], 1) == 0) a.list_next[atomicAdd(a.count_next, 1)] = s;
 }
 
@@ -69,6 +72,29 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
 
   const bool single = tab.n_species == 1 || a.species == nullptr;  // uniform
   if (!single) table_to_lds(ltab);
+  constexpr bool FORCE_ONLY = MODE == kStepForce || MODE == kStepForceEV;
+  const int64_t st = a.st_vel;  // list, reference positions, velocities and forces share the batch stride
+  // per-atom values of the first round, loaded ahead of the staging barrier (a barrier also orders
+  // memory, so loads after it could not overlap the staging latency)
+  struct AtomPre {
+    int nn;
+    double v[3], sc, ref[3];
+  } pre = {};
+  {
+    const int li = first + grp;
+    const bool own = li < ns;
+    const int64_t i = a0 + li;
+    pre.nn = own ? a.n_nbr[i] : 0;
+    if (!FORCE_ONLY && own && lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pre.v[c] = a.vel[c * st + i];
+      pre.sc = a.mass ? a.accel / a.mass[i] : a.accel;
+      if (MODE == kStepMid) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pre.ref[c] = a.ref_pos[c * st + i];
+      }
+    }
+  }
   // 1. stage r_n of the whole system
   double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
   for (int k = tid; k < ns; k += kStepThreads) {
@@ -80,11 +106,9 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                h22 = h[8];
   const uint32_t *__restrict__ nbr = a.nbr;
-  const int64_t st = a.st_vel;  // list, reference positions, velocities and forces share the batch stride
 
   // 3. pair forces of this block's atoms, TL lanes per atom
   constexpr bool EV = MODE == kStepLast || MODE == kStepForceEV;
-  constexpr bool FORCE_ONLY = MODE == kStepForce || MODE == kStepForceEV;
   double e = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // over all rounds
   for (int r = 0; r < a.rounds; ++r) {
     const int base = first + r * APB;
@@ -93,7 +117,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
     const bool own = li < ns;
     const int64_t i = a0 + li;
     const double rx = own ? lx[li] : 0.0, ry = own ? ly[li] : 0.0, rz = own ? lz[li] : 0.0;
-    const int nn = own ? a.n_nbr[i] : 0;
+    const int nn = r == 0 ? pre.nn : (own ? a.n_nbr[i] : 0);
     // (evaluated after the atom's own loads: this order keeps the register count of the loop low)
     const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0 &&
                       h00 > 0.0 && h11 > 0.0 && h22 > 0.0;
@@ -110,8 +134,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
       auto rows = [&](auto diag_c, auto multi_c) {
         constexpr bool DIAG = decltype(diag_c)::value, MULTI = decltype(multi_c)::value;
         const PairCoef pc0 = tab.c[0];  // loop-invariant coefficients in registers
-        for_row_regs<TL, kStepUnroll, kStepRegEntries>(nbr, st, irow, nn, a.max_nbr, lane,
-                                                       [&](const uint32_t *ent, const bool *ok) {
+        for_row_batched<TL, kStepUnroll>(nbr, st, irow, nn, lane, [&](const uint32_t *ent, const bool *ok) {
           double dx[kStepUnroll], dy[kStepUnroll], dz[kStepUnroll], r2[kStepUnroll];
           int jj[kStepUnroll];
           // all LDS reads first, then the shift vectors (independent of them), then the pair vectors
@@ -175,13 +198,13 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
     if (own && lane == 0) {
       T *F = static_cast<T *>(a.force);
       const T Fx = (T)fx, Fy = (T)fy, Fz = (T)fz;
-      const double sc = FORCE_ONLY ? 0.0 : (a.mass ? a.accel / a.mass[i] : a.accel);
+      const double sc = FORCE_ONLY ? 0.0 : (r == 0 ? pre.sc : (a.mass ? a.accel / a.mass[i] : a.accel));
       const double hx = a.half_dt * (double)Fx, hy = a.half_dt * (double)Fy, hz = a.half_dt * (double)Fz;
       double vx = 0.0, vy = 0.0, vz = 0.0;
       if (!FORCE_ONLY) {
-        vx = a.vel[i];
-        vy = a.vel[st + i];
-        vz = a.vel[2 * st + i];
+        vx = r == 0 ? pre.v[0] : a.vel[i];
+        vy = r == 0 ? pre.v[1] : a.vel[st + i];
+        vz = r == 0 ? pre.v[2] : a.vel[2 * st + i];
       }
       // explicit fused multiply-adds: every kick and drift rounds the same way in every kernel
       vx = fma(hx, sc, vx);
@@ -200,7 +223,9 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
         a.pos_out[a.st_out + i] = ny;
         a.pos_out[2 * a.st_out + i] = nz;
         // the cell is unchanged since the list was built (a changed cell was flagged by the first step)
-        const double dx = nx - a.ref_pos[i], dy = ny - a.ref_pos[st + i], dz = nz - a.ref_pos[2 * st + i];
+        const double qx = r == 0 ? pre.ref[0] : a.ref_pos[i], qy = r == 0 ? pre.ref[1] : a.ref_pos[st + i],
+                     qz = r == 0 ? pre.ref[2] : a.ref_pos[2 * st + i];
+        const double dx = nx - qx, dy = ny - qy, dz = nz - qz;
         if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list)) flag_system(a, s);
       } else {
         F[i] = Fx;
@@ -259,12 +284,18 @@ __device__ inline void image_range(double f, double reach, int *lo, int *hi) {
 }
 
 __device__ inline bool shift_ok(int S0, int S1, int S2) {
-  return S0 >= -TS_MAX_IMAGE_SHIFT && S0 <= TS_MAX_IMAGE_SHIFT && S1 >= -TS_MAX_IMAGE_SHIFT &&
-         S1 <= TS_MAX_IMAGE_SHIFT && S2 >= -TS_MAX_IMAGE_SHIFT && S2 <= TS_MAX_IMAGE_SHIFT;
+  // |S| <= 15 for all three: (S + 15) as unsigned is at most 30
+  return ((unsigned)(S0 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT) &
+         ((unsigned)(S1 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT) &
+         ((unsigned)(S2 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT);
 }
 
 __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs a, int chunks_per_sys) {
   extern __shared__ double lds[];
+  // the flagged-system count and this workgroup's first list slot are loaded together (the slot
+  // is read speculatively: the list has room for every system)
+  const int q0 = blockIdx.x / chunks_per_sys;
+  const int s_spec = q0 < a.n_sys ? a.list_cur[q0] : 0;
   const int n_flag = *a.count_cur;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const double rl2 = a.r_list * a.r_list;
@@ -272,7 +303,7 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
   const double *__restrict__ pin = a.pos_in;
   uint32_t *__restrict__ nbr = a.nbr;
   for (int chunk = blockIdx.x; chunk < n_flag * chunks_per_sys; chunk += gridDim.x) {
-    const int s = a.list_cur[chunk / chunks_per_sys];
+    const int s = chunk == (int)blockIdx.x ? s_spec : a.list_cur[chunk / chunks_per_sys];
     const int c0 = (chunk % chunks_per_sys) * kRebuildWaves;
     const int64_t a0 = a.offs[s];
     const int ns = (int)(a.offs[s + 1] - a0);
@@ -346,13 +377,15 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
           const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
           const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
           const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+          // every condition evaluated (bitwise & / |, no short-circuit branches), so the KB
+          // candidate chains of a block group can interleave
           const int fs = s0 != 0 ? s0 : (s1 != 0 ? s1 : s2);
-          bool in = inb && norm2(dx, dy, dz) < rl2 && !(jc == li && s0 == 0 && s1 == 0 && s2 == 0) &&
-                    (!a.half || li < jc || (li == jc && fs > 0));
-          if (in && !shift_ok(s0, s1, s2)) {
-            shift_bad = true;
-            in = false;
-          }
+          const bool self = (jc == li) & (s0 == 0) & (s1 == 0) & (s2 == 0);
+          const bool side = !a.half | (li < jc) | ((li == jc) & (fs > 0));
+          const bool near = inb & (norm2(dx, dy, dz) < rl2) & !self & side;
+          const bool sok = shift_ok(s0, s1, s2);
+          shift_bad |= near & !sok;
+          const bool in = near & sok;
           *e = pack_entry(jc, in ? s0 : 0, in ? s1 : 0, in ? s2 : 0);
           return in;
         };
@@ -486,7 +519,9 @@ int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStrea
   const int64_t work = n_sys * chunks;
   const unsigned grid = (unsigned)(work < 2048 ? work : 2048);
   const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
-  hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, a, chunks);
+  StepArgs b = a;
+  b.n_sys = (int)n_sys;
+  hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, b, chunks);
   TS_LAUNCH_CHECK();
   return TS_OK;
 }

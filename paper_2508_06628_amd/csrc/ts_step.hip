@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
 // Rebuild rows: one wavefront per atom; a workgroup of kRebuildWaves wavefronts handles that many
 // consecutive atoms of one flagged system ("chunks"; chunks_per_sys covers the largest system).
 constexpr int kRebuildWaves = 8;
-constexpr int kRebuildBlocks = 4;  // candidate blocks of 64 one wavefront tests together
+constexpr int kSurvCap = 2 * kWave;  // survivor queue of a wavefront in the wide path
 
 // Candidate images of one (i, j) pair along one lattice direction: integers S with
 // |ds + S| < reach (+ a rounding margin), ds the fractional difference.
@@ -309,13 +309,6 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     const int ns = (int)(a.offs[s + 1] - a0);
     if (c0 >= ns) continue;  // uniform over the workgroup
     const double *__restrict__ h = a.cell + 9 * (int64_t)s;
-    __syncthreads();  // the previous chunk's readers are done with lds
-    double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
-    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-      lx[k] = pin[a0 + k];
-      ly[k] = pin[a.st_in + a0 + k];
-      lz[k] = pin[2 * a.st_in + a0 + k];
-    }
     if (c0 == 0) {
       if (threadIdx.x < 9) a.ref_cell[9 * (int64_t)s + threadIdx.x] = h[threadIdx.x];
       if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.status[TS_STATUS_REBUILDS], 1ull);
@@ -338,80 +331,104 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     const double re0 = a.r_list / (vol / sqrt(c0x * c0x + c0y * c0y + c0z * c0z));
     const double re1 = a.r_list / (vol / sqrt(c1x * c1x + c1y * c1y + c1z * c1z));
     const double re2 = a.r_list / (vol / sqrt(c2x * c2x + c2y * c2y + c2z * c2z));
-    // every lattice direction wider than 2 r_list: at most one image of j is within r_list of i,
-    // the nearest one, S = -rint(fractional difference) (a tie at |f + S| = 1/2 is out of reach)
-    const bool wide = re0 < 0.5 - 1e-6 && re1 < 0.5 - 1e-6 && re2 < 0.5 - 1e-6;
-    const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0;
+    // every lattice direction comfortably wider than 2 r_list: at most one image of j is within
+    // r_list of i, the nearest one, S = -rint(fractional difference) (a tie at |f + S| = 1/2 is out
+    // of reach), and the float32 prefilter on wrapped fractional coordinates below is safe
+    const bool wide = re0 < 0.5 - 1e-3 && re1 < 0.5 - 1e-3 && re2 < 0.5 - 1e-3;
+    __syncthreads();  // the previous chunk's readers are done with lds
+    double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
+    float4 *sf = reinterpret_cast<float4 *>(lds);                          // wide: wrapped fractional
+    int *surv = reinterpret_cast<int *>(lds + 2 * ns) + wave * kSurvCap;  // wide: survivor queue
+    if (wide) {
+      for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+        const double x = pin[a0 + k], y = pin[a.st_in + a0 + k], z = pin[2 * a.st_in + a0 + k];
+        const double f0 = x * i00 + y * i10 + z * i20, f1 = x * i01 + y * i11 + z * i21,
+                     f2 = x * i02 + y * i12 + z * i22;
+        sf[k] = make_float4((float)(f0 - floor(f0)), (float)(f1 - floor(f1)), (float)(f2 - floor(f2)), 0.0f);
+      }
+    } else {
+      for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+        lx[k] = pin[a0 + k];
+        ly[k] = pin[a.st_in + a0 + k];
+        lz[k] = pin[2 * a.st_in + a0 + k];
+      }
+    }
     __syncthreads();
     const int li = c0 + wave;
     if (li >= ns) continue;  // uniform over the wavefront; no block barrier follows before the loop top
     const int64_t i = a0 + li;
-    const double rx = lx[li], ry = ly[li], rz = lz[li];
+    const double rx = pin[a0 + li], ry = pin[a.st_in + a0 + li], rz = pin[2 * a.st_in + a0 + li];
     int cnt = 0;
     bool shift_bad = false;
     if (wide) {
-      // one candidate per (i, j): two blocks of 64 candidates per iteration, evaluated without
-      // branches; the pair vector is computed exactly as in the general path below
-      auto scan = [&](auto diag_c) {
-        constexpr bool DIAG = decltype(diag_c)::value;
-        auto cand = [&](int j, uint32_t *e) -> bool {
-          const bool inb = j < ns;
-          const int jc = inb ? j : li;
-          const double drx = lx[jc] - rx, dry = ly[jc] - ry, drz = lz[jc] - rz;
-          double f0, f1, f2;
-          if (DIAG) {
-            f0 = drx * i00;
-            f1 = dry * i11;
-            f2 = drz * i22;
-          } else {
-            f0 = drx * i00 + dry * i10 + drz * i20;
-            f1 = drx * i01 + dry * i11 + drz * i21;
-            f2 = drx * i02 + dry * i12 + drz * i22;
-          }
-          // nearest integers without rounding or conversion instructions: t = f + 1.5 2^52 rounds
-          // f to an integer n (ties to even, like rint) for |f| < 2^51, and the low word of t is n
-          constexpr double kRound = 6755399441055744.0;
-          const double t0 = f0 + kRound, t1 = f1 + kRound, t2 = f2 + kRound;
-          const double S0 = kRound - t0, S1 = kRound - t1, S2 = kRound - t2;  // -rint(f), exact
-          const int s0 = -__double2loint(t0), s1 = -__double2loint(t1), s2 = -__double2loint(t2);
-          const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
-          const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
-          const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
-          // every condition evaluated (bitwise & / |, no short-circuit branches), so the KB
-          // candidate chains of a block group can interleave
-          const int fs = s0 != 0 ? s0 : (s1 != 0 ? s1 : s2);
-          const bool self = (jc == li) & (s0 == 0) & (s1 == 0) & (s2 == 0);
-          const bool side = !a.half | (li < jc) | ((li == jc) & (fs > 0));
-          const bool near = inb & (norm2(dx, dy, dz) < rl2) & !self & side;
-          const bool sok = shift_ok(s0, s1, s2);
-          shift_bad |= near & !sok;
-          const bool in = near & sok;
-          *e = pack_entry(jc, in ? s0 : 0, in ? s1 : 0, in ? s2 : 0);
-          return in;
-        };
-        // KB blocks of 64 candidates: all KB tests first (independent chains), then the
-        // compaction of each block in j order
-        auto blocks = [&](int j0, auto kb_c) {
-          constexpr int KB = decltype(kb_c)::value;
-          uint32_t e[KB];
-          bool c[KB];
-#pragma unroll
-          for (int b = 0; b < KB; ++b) c[b] = cand(j0 + b * kWave + lane, &e[b]);
-#pragma unroll
-          for (int b = 0; b < KB; ++b) {
-            const uint64_t m = __ballot(c[b]);
-            const int p = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-            if (c[b] && p < a.max_nbr) nbr[row_index(p, i, st)] = e[b];
-            cnt += __popcll(m);
-          }
-        };
-        int j0 = 0;
-        for (; j0 + kRebuildBlocks * kWave <= ns; j0 += kRebuildBlocks * kWave)
-          blocks(j0, std::integral_constant<int, kRebuildBlocks>{});
-        for (; j0 < ns; j0 += kWave) blocks(j0, std::integral_constant<int, 1>{});
+      // Pass 1, float32: the nearest-image distance from wrapped fractional coordinates.  A candidate
+      // survives below r_list + delta, where delta bounds the float32 rounding of the fractional
+      // coordinates and of the distance (a few 1e-5 A at most) with a wide margin, so every pair
+      // within r_list survives.  Survivors are queued in j order.
+      // Pass 2, float64: each batch of up to 64 survivors takes the exact test of the general path
+      // (same pair vector arithmetic) and is compacted into the row in queue order.
+      const float4 fi = sf[li];
+      const float g00 = (float)h00, g01 = (float)h01, g02 = (float)h02, g10 = (float)h10, g11 = (float)h11,
+                  g12 = (float)h12, g20 = (float)h20, g21 = (float)h21, g22 = (float)h22;
+      const double rowsum = sqrt(h00 * h00 + h01 * h01 + h02 * h02) + sqrt(h10 * h10 + h11 * h11 + h12 * h12) +
+                            sqrt(h20 * h20 + h21 * h21 + h22 * h22);
+      const double rc = a.r_list + 1e-4 + 4e-6 * rowsum;
+      const float rc2f = (float)(rc * rc);
+      int pend = 0;
+      auto exact = [&](int n) {  // the first n queued survivors
+        __builtin_amdgcn_wave_barrier();  // queue writes of other lanes before these reads
+        const int j = lane < n ? surv[lane] : li;
+        const double drx = pin[a0 + j] - rx, dry = pin[a.st_in + a0 + j] - ry, drz = pin[2 * a.st_in + a0 + j] - rz;
+        const double f0 = drx * i00 + dry * i10 + drz * i20, f1 = drx * i01 + dry * i11 + drz * i21,
+                     f2 = drx * i02 + dry * i12 + drz * i22;
+        // nearest integers without rounding or conversion instructions: t = f + 1.5 2^52 rounds f to
+        // an integer n (ties to even, like rint) for |f| < 2^51, and the low word of t is n
+        constexpr double kRound = 6755399441055744.0;
+        const double t0 = f0 + kRound, t1 = f1 + kRound, t2 = f2 + kRound;
+        const double S0 = kRound - t0, S1 = kRound - t1, S2 = kRound - t2;  // -rint(f), exact
+        const int s0 = -__double2loint(t0), s1 = -__double2loint(t1), s2 = -__double2loint(t2);
+        const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+        const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+        const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+        const int fs = s0 != 0 ? s0 : (s1 != 0 ? s1 : s2);
+        const bool self = (j == li) & (s0 == 0) & (s1 == 0) & (s2 == 0);
+        const bool side = !a.half | (li < j) | ((li == j) & (fs > 0));
+        const bool near = (lane < n) & (norm2(dx, dy, dz) < rl2) & !self & side;
+        const bool sok = shift_ok(s0, s1, s2);
+        shift_bad |= near & !sok;
+        const bool in = near & sok;
+        const uint64_t m = __ballot(in);
+        const int p = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+        if (in && p < a.max_nbr) nbr[row_index(p, i, st)] = pack_entry(j, s0, s1, s2);
+        cnt += __popcll(m);
       };
-      if (diag) scan(std::true_type{});
-      else scan(std::false_type{});
+      for (int j0 = 0; j0 < ns; j0 += kWave) {
+        const int j = j0 + lane;
+        const float4 fj = sf[j < ns ? j : li];
+        float dfx = fj.x - fi.x, dfy = fj.y - fi.y, dfz = fj.z - fi.z;
+        dfx -= rintf(dfx);
+        dfy -= rintf(dfy);
+        dfz -= rintf(dfz);
+        const float dx = dfx * g00 + dfy * g10 + dfz * g20;
+        const float dy = dfx * g01 + dfy * g11 + dfz * g21;
+        const float dz = dfx * g02 + dfy * g12 + dfz * g22;
+        const bool pass = (j < ns) & (dx * dx + dy * dy + dz * dz < rc2f);
+        const uint64_t m = __ballot(pass);
+        const int q = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+        if (pass) surv[q] = j;
+        pend += __popcll(m);
+        if (pend >= kWave) {
+          exact(kWave);
+          // move the overflow (fewer than 64 entries) to the front of the queue
+          const int rest = pend - kWave;
+          const int moved = lane < rest ? surv[kWave + lane] : 0;
+          __builtin_amdgcn_wave_barrier();
+          if (lane < rest) surv[lane] = moved;
+          __builtin_amdgcn_wave_barrier();
+          pend = rest;
+        }
+      }
+      if (pend > 0) exact(pend);
     }
     for (int j0 = 0; j0 < (wide ? 0 : ns); j0 += kWave) {
       const int j = j0 + lane;
@@ -518,7 +535,10 @@ int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStrea
   const int chunks = (int)ceil_div(max_atoms, kRebuildWaves);
   const int64_t work = n_sys * chunks;
   const unsigned grid = (unsigned)(work < 2048 ? work : 2048);
-  const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
+  // general path: float64 positions; wide path: float4 fractional coordinates + survivor queues
+  const size_t shm_general = (size_t)3 * sizeof(double) * (size_t)max_atoms;
+  const size_t shm_wide = (size_t)2 * sizeof(double) * (size_t)max_atoms + sizeof(int) * kSurvCap * kRebuildWaves;
+  const size_t shm = shm_general > shm_wide ? shm_general : shm_wide;
   StepArgs b = a;
   b.n_sys = (int)n_sys;
   hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, b, chunks);

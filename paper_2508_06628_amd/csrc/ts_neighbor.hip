@@ -180,29 +180,32 @@ __global__ void k_nl_assign(int64_t n, int64_t stride, const int32_t *__restrict
 // One block per system: exclusive scan of the bin counts -> global start of each bin.
 __global__ void __launch_bounds__(256) k_nl_scan(const int64_t *__restrict__ offs, const NlGeom *__restrict__ geom,
                                                  const int32_t *__restrict__ count, int32_t *__restrict__ start) {
+  // thread t owns a contiguous segment of the system's bins: segment totals, one block-wide
+  // exclusive scan of the 256 totals (wavefront shuffles, one barrier), then each thread writes its
+  // segment's starts sequentially
   const int s = blockIdx.x;
   if (!geom[s].active) return;
   const int nb = geom[s].n[0] * geom[s].n[1] * geom[s].n[2];
   const int64_t base = 2 * offs[s] + s;
-  __shared__ int32_t part[256];
-  __shared__ int32_t carry;
-  if (threadIdx.x == 0) carry = (int32_t)offs[s];
+  const int seg = (nb + 255) / 256;
+  const int b0 = min((int)threadIdx.x * seg, nb), b1 = min(b0 + seg, nb);
+  int32_t sum = 0;
+  for (int b = b0; b < b1; ++b) sum += count[base + b];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  int32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  __shared__ int32_t wtot[4];
+  if (lane == kWave - 1) wtot[wave] = incl;
   __syncthreads();
-  for (int c0 = 0; c0 < nb; c0 += 256) {
-    const int b = c0 + threadIdx.x;
-    const int32_t v = b < nb ? count[base + b] : 0;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-      const int32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-      __syncthreads();
-      part[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (b < nb) start[base + b] = carry + part[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 255) carry += part[255];
-    __syncthreads();
+  int32_t ex = (int32_t)offs[s] + incl - sum;
+  for (int w = 0; w < wave; ++w) ex += wtot[w];
+  for (int b = b0; b < b1; ++b) {
+    start[base + b] = ex;
+    ex += count[base + b];
   }
 }
 

@@ -4,9 +4,11 @@ One step = one velocity-Verlet step of the whole batch (device-side neighbor val
 rebuilds included), FP32 pair arithmetic with FP64 integration, the step loop replayed from
 hipGraphs.  Prints one JSON line with atom-steps/s, the force kernel's roofline position, the
 plain one-system-per-launch path on the same GPU, the adjoint (trajectory-gradient) throughput
-of the 16 x 864 differentiable run, and the FP64 CPU oracle timed on the host.
+of the 16 x 864 differentiable run, the batched FIRE relaxation of the uneven 512-system copper
+batch (one persistent launch), the soft-sphere jamming batch (FIRE, then NVE), and the FP64 CPU
+oracle timed on the host.
 
-    python bench.py [--steps K] [--warmup W] [--chunk C] [--no-plain] [--no-adjoint] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--chunk C] [--no-plain] [--no-adjoint] [--no-fire] [--no-cpu]
     python bench.py --profile-kernels --lanes L     # short launch sequence for rocprofv3
 """
 from __future__ import annotations
@@ -154,6 +156,85 @@ def adjoint_throughput(api, torch, n_systems, n_steps, checkpoint):
                 loss=float(eng.loss.item()), dL_deps=de, dL_dsigma=ds)
 
 
+def fire_copper(api, torch, max_iter=20000):
+    """Batched FIRE of positions and cell on the uneven 512-system Morse copper batch, in one
+    persistent launch, until every system has max |F| < fmax (and the cell force too)."""
+    from workloads import copper_uneven_batch
+    w = copper_uneven_batch(512, seed=2)
+    pot = w.potential
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=2, margin=1.2)
+    pp = api.pair_params_from_spec(pot, w.pair_prec)
+    cfgd = dict(w.extra["fire"])
+    cfgd["relax_cell"] = True
+    cfgd["max_iter"] = max_iter
+    cfg = api.fire_config(**cfgd)
+    fs = api.FireState(b, cfg)
+    F = api.force_buffer(b, w.pair_prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    api.ts_fire_step(b, fs, cfg, nl, pp, max_iter, F, persistent=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    it = fs.n_iter.cpu().numpy()
+    work = float((it * np.diff(b.h_offsets)).sum())
+    return dict(workload=f"copper_morse_fire_cell_{w.n_systems}_uneven", n_atoms=b.n_atoms, seconds=round(ms * 1e-3, 4),
+                converged=int(fs.converged.sum().item()), n_systems=w.n_systems, iterations_mean=round(float(it.mean()), 1),
+                iterations_max=int(it.max()), value=round(work / (ms * 1e-3), 1), unit="atom-iterations/s",
+                list_rebuilds=int(nl.read_status()[2]))
+
+
+def soft_sphere(api, torch, fire_iters=4000, nve_steps=2000, chunk=100):
+    """Soft-sphere jamming batch (8 x 32000, binary): batched FIRE (capped at fire_iters), then NVE
+    at T = 1e-4 (reduced units) from Maxwell-Boltzmann velocities."""
+    from workloads import maxwell_boltzmann, soft_sphere_jamming_batch
+    w = soft_sphere_jamming_batch(8, 32000, seed=4)
+    pot = w.potential
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=2, margin=1.3)
+    pp = api.pair_params_from_spec(pot, w.pair_prec)
+    cfg = api.fire_config(**w.extra["fire"])
+    fs = api.FireState(b, cfg)
+    F = api.force_buffer(b, w.pair_prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    done = 0
+    while done < fire_iters:
+        api.ts_fire_step(b, fs, cfg, nl, pp, 500, F)
+        done += 500
+        if fs.converged.all().item():
+            break
+    e1.record()
+    torch.cuda.synchronize()
+    fire_ms = e0.elapsed_time(e1)
+    it = fs.n_iter.cpu().numpy()
+    fire_work = float((it * np.diff(b.h_offsets)).sum())
+    rng = np.random.default_rng(5)
+    v = maxwell_boltzmann(rng, w.mass, w.extra["nve_temperature"], k_b=1.0, accel=1.0)
+    b.vel.copy_(torch.tensor(np.ascontiguousarray(v.T), dtype=torch.float64, device=b.device))
+    api.ts_pair_forces(b, nl, pp, F)
+    api.ts_nve_step(b, nl, pp, w.dt, w.accel, chunk, F, use_graph=True)  # instantiate the graph
+    torch.cuda.synchronize()
+    nl.status.zero_()
+    e0.record()
+    for _ in range(nve_steps // chunk):
+        api.ts_nve_step(b, nl, pp, w.dt, w.accel, chunk, F, use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    nve_ms = e0.elapsed_time(e1)
+    st = nl.read_status()
+    return dict(workload="soft_sphere_binary_8x32000", n_atoms=b.n_atoms,
+                fire=dict(seconds=round(fire_ms * 1e-3, 4), iterations=int(it.max()),
+                          converged=int(fs.converged.sum().item()), value=round(fire_work / (fire_ms * 1e-3), 1),
+                          unit="atom-iterations/s"),
+                nve=dict(steps=nve_steps, ms_per_step=round(nve_ms / nve_steps, 5),
+                         value=round(w.n_atoms * nve_steps / (nve_ms * 1e-3), 1), unit="atom-steps/s",
+                         system_rebuilds=int(st[2])))
+
+
 def cpu_baseline(w, steps=2):
     """The FP64 oracle (brute-force pair search) on one system of the workload, on the host."""
     from oracle import integrate
@@ -203,6 +284,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fire", action="store_true", help="skip the copper FIRE and soft-sphere workloads")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="run a short fixed launch sequence for rocprofv3 instead of the benchmark")
     args = ap.parse_args()
@@ -257,6 +339,11 @@ def main():
         a = adjoint_throughput(api, torch, 16, args.adjoint_steps, 50)
         out["adjoint"] = a
         log(f"adjoint: {a['value']:.4g} atom-steps/s")
+    if not args.no_fire:
+        out["fire_copper"] = fire_copper(api, torch)
+        log(f"copper FIRE: {out['fire_copper']}")
+        out["soft_sphere"] = soft_sphere(api, torch)
+        log(f"soft sphere: {out['soft_sphere']}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
         log(f"cpu oracle: {out['cpu_baseline']['value']} atom-steps/s")

@@ -57,6 +57,7 @@ __device__ inline double block_max(double v, double *sh) {
 // The slot of chunk c of system s is s + floor((a0_s + kFireChunk c) / kFireChunk): unique, and at
 // most S + N / kFireChunk + 1 slots of 4 doubles.
 constexpr int kFireChunk = 256;
+constexpr int64_t kFireTailChunk = 32;  // tail iterations between two host checks
 
 __device__ inline int64_t fire_slot(int s, int64_t a0, int c) { return s + (a0 + (int64_t)kFireChunk * c) / kFireChunk; }
 
@@ -151,7 +152,8 @@ __global__ void __launch_bounds__(kWave) k_fire_decide(FireArgs a, const double 
   if (conv) {
     a.converged[s] = 1;
     skip = 1.0;
-  } else if (final_check || a.n_iter[s] >= c.max_iter) {
+  } else if (final_check || a.n_iter[s] >= c.max_iter ||
+             (a.iter_start && a.budget >= 0 && a.n_iter[s] - a.iter_start[s] >= a.budget)) {
     skip = 1.0;
   } else {
     double dt = a.dt[s], al = a.alpha[s];
@@ -272,6 +274,21 @@ static int launch_fire_update(const FireArgs &fa, bool cell, int final_check, in
   return TS_OK;
 }
 
+// Systems still open (not converged, below max_iter and below this call's budget) -> *out.
+__global__ void __launch_bounds__(256) k_fire_open(FireArgs a, int64_t n_sys, int32_t *out) {
+  __shared__ int32_t tot[4];
+  int32_t c = 0;
+  for (int64_t s = threadIdx.x; s < n_sys; s += blockDim.x) {
+    const bool budget_left = !a.iter_start || a.budget < 0 || a.n_iter[s] - a.iter_start[s] < a.budget;
+    c += (!a.converged[s] && a.n_iter[s] < a.cfg.max_iter && budget_left) ? 1 : 0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if (threadIdx.x % kWave == 0) tot[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = tot[0] + tot[1] + tot[2] + tot[3];
+}
+
 FireArgs make_fire_args(const ts_batch *b, const ts_fire_state *fs, const ts_fire_config *cfg, void *force,
                         double *virial) {
   FireArgs fa;
@@ -292,7 +309,38 @@ FireArgs make_fire_args(const ts_batch *b, const ts_fire_state *fs, const ts_fir
   fa.deform_vel = fs->deform_vel;
   fa.ref_cell = fs->ref_cell;
   fa.cfg = *cfg;
+  fa.iter_start = nullptr;
+  fa.budget = -1;
   return fa;
+}
+
+// n_iter FIRE iterations of every open system with the per-iteration kernels, then a convergence
+// check of the final positions.
+static int fire_iterations(const ts_batch *batch, const ts_fire_state *fs, const ts_fire_config *cfg,
+                           ts_neighbor_list *nl, const ts_pair_params *pp, const FireArgs &fa, int64_t n_iter,
+                           void *force, double *energy, double *virial, int64_t max_atoms, hipStream_t st) {
+  const bool cell = cfg->relax_cell != 0;
+  const PairTable tab = make_table(pp);
+  const int64_t S = batch->n_systems;
+  // per-chunk partial sums in the list workspace's second adjoint buffer (6 N doubles, free during
+  // a relaxation) and the per-system coefficients in the state's scratch after the virial slots
+  const NlWork w = nl_work(nl->workspace, batch->n_atoms, S);
+  double *part = w.adj_alt;
+  double *coef = fs->scratch + 9 * S;
+  for (int64_t it = 0; it <= n_iter; ++it) {
+    const bool last = it == n_iter;
+    int rc = nl_update(batch, nl, 0, max_atoms, st);
+    if (rc != TS_OK) return rc;
+    double *e = last ? energy : nullptr;
+    const bool ev = cell || (last && (energy || virial));
+    rc = launch_forces(make_force_args(batch, nl, force, e, ev ? fa.virial : nullptr, fs->converged), S, tab,
+                       pp->prec, ev, st);
+    if (rc != TS_OK) return rc;
+    rc = pp->prec == TS_PAIR_F32 ? launch_fire_update<float>(fa, cell, last ? 1 : 0, S, max_atoms, part, coef, st)
+                                 : launch_fire_update<double>(fa, cell, last ? 1 : 0, S, max_atoms, part, coef, st);
+    if (rc != TS_OK) return rc;
+  }
+  return TS_OK;
 }
 
 }  // namespace ts
@@ -313,31 +361,35 @@ extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_f
       TS_CHECK_ARG(batch->h_sys_offsets[s + 1] > batch->h_sys_offsets[s]);
   }
   hipStream_t st = ts::as_stream(stream);
-  if (persistent && max_atoms <= ts::kLdsMaxAtoms)
-    return ts::fire_persistent(batch, fs, cfg, nl, pp, n_iter, force, energy, virial, max_atoms, st);
-  TS_CHECK_ARG(n_iter >= 1);
-  const ts::PairTable tab = ts::make_table(pp);
   const int64_t S = batch->n_systems;
   double *vir = virial ? virial : fs->scratch;  // scratch holds [S][9] when the caller wants no virial
-  const ts::FireArgs fa = ts::make_fire_args(batch, fs, cfg, force, vir);
-  // per-chunk partial sums in the list workspace's second adjoint buffer (6 N doubles, free during
-  // a relaxation) and the per-system coefficients in the state's scratch after the virial slots
-  const ts::NlWork w = ts::nl_work(nl->workspace, batch->n_atoms, S);
-  double *part = w.adj_alt;
-  double *coef = fs->scratch + 9 * S;
-  for (int64_t it = 0; it <= n_iter; ++it) {
-    const bool last = it == n_iter;
-    rc = ts::nl_update(batch, nl, 0, max_atoms, st);
-    if (rc != TS_OK) return rc;
-    double *e = last ? energy : nullptr;
-    const bool ev = cell || (last && (energy || virial));
-    rc = ts::launch_forces(ts::make_force_args(batch, nl, force, e, ev ? vir : nullptr, fs->converged),
-                           batch->n_systems, tab, pp->prec, ev, st);
-    if (rc != TS_OK) return rc;
-    rc = pp->prec == TS_PAIR_F32
-             ? ts::launch_fire_update<float>(fa, cell, last ? 1 : 0, S, max_atoms, part, coef, st)
-             : ts::launch_fire_update<double>(fa, cell, last ? 1 : 0, S, max_atoms, part, coef, st);
-    if (rc != TS_OK) return rc;
+  ts::FireArgs fa = ts::make_fire_args(batch, fs, cfg, force, vir);
+  if (persistent && max_atoms <= ts::kLdsMaxAtoms) {
+    // n_iter at the start of the call, for the per-call budget of the tail (scratch slots 31 S..32 S)
+    int64_t *iter_start = reinterpret_cast<int64_t *>(fs->scratch + 31 * S);
+    TS_HIP(hipMemcpyAsync(iter_start, fs->n_iter, sizeof(int64_t) * S, hipMemcpyDeviceToDevice, st));
+    bool handed_off = false;
+    rc = ts::fire_persistent(batch, fs, cfg, nl, pp, n_iter, force, energy, virial, max_atoms, true, &handed_off, st);
+    if (rc != TS_OK || !handed_off) return rc;
+    // the tail: systems still iterating when the persistent launch stopped (it stops once most of
+    // its workgroups are idle) continue with the per-iteration kernels, which spread every system
+    // over many workgroups; the host checks after each chunk whether any system is still open
+    fa.iter_start = iter_start;
+    fa.budget = n_iter;
+    int32_t *d_open = reinterpret_cast<int32_t *>(ts::nl_work(nl->workspace, batch->n_atoms, S).flags3) + 6 * S + 2;
+    for (;;) {
+      hipLaunchKernelGGL(ts::k_fire_open, dim3(1), dim3(256), 0, st, fa, S, d_open);
+      TS_LAUNCH_CHECK();
+      int32_t open = 0;
+      TS_HIP(hipMemcpyAsync(&open, d_open, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      TS_HIP(hipStreamSynchronize(st));
+      if (open == 0) return TS_OK;
+      rc = ts::fire_iterations(batch, fs, cfg, nl, pp, fa, ts::kFireTailChunk, force, energy, virial, max_atoms, st);
+      if (rc != TS_OK) return rc;
+    }
   }
+  TS_CHECK_ARG(n_iter >= 1);
+  rc = ts::fire_iterations(batch, fs, cfg, nl, pp, fa, n_iter, force, energy, virial, max_atoms, st);
+  if (rc != TS_OK) return rc;
   return TS_OK;
 }

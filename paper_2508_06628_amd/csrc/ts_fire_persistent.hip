@@ -19,6 +19,7 @@ namespace ts {
 constexpr int kPT = 512;          // threads per workgroup
 constexpr int kPW = kPT / kWave;  // wavefronts per workgroup
 constexpr int kPR = 16;           // reduced quantities: fmax2 P vv gg E W[9] (2 spare)
+constexpr int kPSurv = 2 * kWave;  // survivor queue of a wavefront in the wide-cell rebuild
 
 struct FirePArgs {
   FireArgs f;
@@ -35,12 +36,17 @@ struct FirePArgs {
   int32_t *queue;    // [1] head of the work queue (zeroed before launch)
   int32_t *order;    // [S] systems, largest first
   int64_t budget;    // iterations per system in this call (< 0: until converged or max_iter)
+  int32_t *idle;     // [1] workgroups that found the queue empty (zeroed before launch)
+  int32_t idle_limit;  // > 0: stop iterating once idle >= idle_limit (the tail goes elsewhere)
 };
 
 // order[rank] = s with systems ranked by decreasing size (ties by index)
 __global__ void k_fire_order(int64_t n_sys, const int64_t *offs, int32_t *order, int32_t *queue) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) *queue = 0;
+  if (s == 0) {
+    queue[0] = 0;  // head
+    queue[1] = 0;  // idle workgroups
+  }
   if (s >= n_sys) return;
   const int64_t ns = offs[s + 1] - offs[s];
   int64_t rank = 0;
@@ -89,7 +95,10 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(PairTable tab, FirePArg
     }
     __syncthreads();
     const int s = s_sys;
-    if (s < 0) break;
+    if (s < 0) {
+      if (tid == 0) atomicAdd(a.idle, 1);
+      break;
+    }
     const int64_t a0 = a.f.offs[s];
     const int ns = (int)(a.f.offs[s + 1] - a0);
     if (a.f.converged[s] || ns == 0) {
@@ -180,7 +189,91 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(PairTable tab, FirePArg
         __syncthreads();
         const double h00 = sh[0], h01 = sh[1], h02 = sh[2], h10 = sh[3], h11 = sh[4], h12 = sh[5], h20 = sh[6],
                      h21 = sh[7], h22 = sh[8];
-        for (int li = wave; li < ns; li += kPW) {
+        // every lattice direction comfortably wider than 2 r_list: one candidate image per pair, and a
+        // float32 prefilter on wrapped fractional coordinates ahead of the exact float64 test
+        const bool wide = sh[18] < 0.5 - 1e-3 && sh[19] < 0.5 - 1e-3 && sh[20] < 0.5 - 1e-3;
+        if (wide) {
+          float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns);
+          for (int k = tid; k < ns; k += kPT) {
+            const double x = lx[k], y = ly[k], z = lz[k];
+            const double f0 = x * sh[9] + y * sh[12] + z * sh[15], f1 = x * sh[10] + y * sh[13] + z * sh[16],
+                         f2 = x * sh[11] + y * sh[14] + z * sh[17];
+            sf[k] = make_float4((float)(f0 - floor(f0)), (float)(f1 - floor(f1)), (float)(f2 - floor(f2)), 0.0f);
+          }
+          __syncthreads();
+          int *surv = reinterpret_cast<int *>(sf + ns) + wave * kPSurv;
+          const float g00 = (float)h00, g01 = (float)h01, g02 = (float)h02, g10 = (float)h10, g11 = (float)h11,
+                      g12 = (float)h12, g20 = (float)h20, g21 = (float)h21, g22 = (float)h22;
+          const double rowsum = sqrt(h00 * h00 + h01 * h01 + h02 * h02) + sqrt(h10 * h10 + h11 * h11 + h12 * h12) +
+                                sqrt(h20 * h20 + h21 * h21 + h22 * h22);
+          const double rcut = a.r_list + 1e-4 + 4e-6 * rowsum;
+          const float rc2f = (float)(rcut * rcut);
+          for (int li = wave; li < ns; li += kPW) {
+            const int64_t i = a0 + li;
+            const double rx = lx[li], ry = ly[li], rz = lz[li];
+            const float4 fi = sf[li];
+            int cnt = 0, pend = 0;
+            auto exact = [&](int n) {  // the first n queued survivors, in queue (= j) order
+              __builtin_amdgcn_wave_barrier();
+              const int j = lane < n ? surv[lane] : li;
+              const double drx = lx[j] - rx, dry = ly[j] - ry, drz = lz[j] - rz;
+              const double f0 = drx * sh[9] + dry * sh[12] + drz * sh[15];
+              const double f1 = drx * sh[10] + dry * sh[13] + drz * sh[16];
+              const double f2 = drx * sh[11] + dry * sh[14] + drz * sh[17];
+              constexpr double kRound = 6755399441055744.0;  // f + 1.5 2^52 rounds f like rint
+              const double t0 = f0 + kRound, t1 = f1 + kRound, t2 = f2 + kRound;
+              const double S0 = kRound - t0, S1 = kRound - t1, S2 = kRound - t2;
+              const int s0 = -__double2loint(t0), s1 = -__double2loint(t1), s2 = -__double2loint(t2);
+              const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+              const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+              const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+              const bool self = (j == li) & (s0 == 0) & (s1 == 0) & (s2 == 0);
+              const bool sok = ((unsigned)(s0 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT) &
+                               ((unsigned)(s1 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT) &
+                               ((unsigned)(s2 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT);
+              const bool in = (lane < n) & (norm2(dx, dy, dz) < rl2) & !self & sok;
+              const uint64_t m = __ballot(in);
+              const int p = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+              if (in && p < a.max_nbr) a.nbr[row_index(p, i, st)] = pack_entry(j, s0, s1, s2);
+              cnt += __popcll(m);
+            };
+            for (int j0 = 0; j0 < ns; j0 += kWave) {
+              const int j = j0 + lane;
+              const float4 fj = sf[j < ns ? j : li];
+              float dfx = fj.x - fi.x, dfy = fj.y - fi.y, dfz = fj.z - fi.z;
+              dfx -= rintf(dfx);
+              dfy -= rintf(dfy);
+              dfz -= rintf(dfz);
+              const float dx = dfx * g00 + dfy * g10 + dfz * g20;
+              const float dy = dfx * g01 + dfy * g11 + dfz * g21;
+              const float dz = dfx * g02 + dfy * g12 + dfz * g22;
+              const bool pass = (j < ns) & (dx * dx + dy * dy + dz * dz < rc2f);
+              const uint64_t m = __ballot(pass);
+              const int q = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+              if (pass) surv[q] = j;
+              pend += __popcll(m);
+              if (pend >= kWave) {
+                exact(kWave);
+                const int rest = pend - kWave;
+                const int moved = lane < rest ? surv[kWave + lane] : 0;
+                __builtin_amdgcn_wave_barrier();
+                if (lane < rest) surv[lane] = moved;
+                __builtin_amdgcn_wave_barrier();
+                pend = rest;
+              }
+            }
+            if (pend > 0) exact(pend);
+            if (lane == 0) {
+              a.n_nbr[i] = cnt < a.max_nbr ? cnt : a.max_nbr;
+              a.ref_pos[i] = rx;
+              a.ref_pos[st + i] = ry;
+              a.ref_pos[2 * st + i] = rz;
+              status_raise(a.status, TS_STATUS_MAX_NBR, cnt);
+              if (cnt > a.max_nbr) status_raise(a.status, TS_STATUS_OVERFLOW, 1);
+            }
+          }
+        }
+        for (int li = wide ? ns : wave; li < ns; li += kPW) {
           const int64_t i = a0 + li;
           const double rx = lx[li], ry = ly[li], rz = lz[li];
           int cnt = 0;
@@ -197,23 +290,24 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(PairTable tab, FirePArg
               const double f0 = drx * sh[9] + dry * sh[12] + drz * sh[15];
               const double f1 = drx * sh[10] + dry * sh[13] + drz * sh[16];
               const double f2 = drx * sh[11] + dry * sh[14] + drz * sh[17];
-              lo0 = (int)ceil(-f0 - sh[18] - 1e-9);
-              hi0 = (int)floor(-f0 + sh[18] + 1e-9);
-              lo1 = (int)ceil(-f1 - sh[19] - 1e-9);
-              hi1 = (int)floor(-f1 + sh[19] + 1e-9);
-              lo2 = (int)ceil(-f2 - sh[20] - 1e-9);
-              hi2 = (int)floor(-f2 + sh[20] + 1e-9);
+              bool clipped = false;  // reported like an out-of-range shift (the list is then incomplete)
+              image_range(f0, sh[18], &lo0, &hi0, &clipped);
+              image_range(f1, sh[19], &lo1, &hi1, &clipped);
+              image_range(f2, sh[20], &lo2, &hi2, &clipped);
+              if (clipped) status_raise(a.status, TS_STATUS_SHIFT, 1);
               for (int S0 = lo0; S0 <= hi0; ++S0)
                 for (int S1 = lo1; S1 <= hi1; ++S1)
                   for (int S2 = lo2; S2 <= hi2; ++S2) {
                     if (j == li && S0 == 0 && S1 == 0 && S2 == 0) continue;
-                    if (S0 < -TS_MAX_IMAGE_SHIFT || S0 > TS_MAX_IMAGE_SHIFT || S1 < -TS_MAX_IMAGE_SHIFT ||
-                        S1 > TS_MAX_IMAGE_SHIFT || S2 < -TS_MAX_IMAGE_SHIFT || S2 > TS_MAX_IMAGE_SHIFT)
-                      continue;
                     const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
                     const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
                     const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
                     if (!(norm2(dx, dy, dz) < rl2)) continue;
+                    if (S0 < -TS_MAX_IMAGE_SHIFT || S0 > TS_MAX_IMAGE_SHIFT || S1 < -TS_MAX_IMAGE_SHIFT ||
+                        S1 > TS_MAX_IMAGE_SHIFT || S2 < -TS_MAX_IMAGE_SHIFT || S2 > TS_MAX_IMAGE_SHIFT) {
+                      status_raise(a.status, TS_STATUS_SHIFT, 1);  // in range but not packable
+                      continue;
+                    }
                     if (c == 0) e1 = pack_entry(j, S0, S1, S2);
                     ++c;
                   }
@@ -376,7 +470,9 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(PairTable tab, FirePArg
         if (conv) {
           a.f.converged[s] = 1;
           stop = 1.0;
-        } else if (a.f.n_iter[s] >= cf.max_iter || (a.budget >= 0 && it >= a.budget)) {
+        } else if (a.f.n_iter[s] >= cf.max_iter || (a.budget >= 0 && it >= a.budget) ||
+                   (a.idle_limit > 0 &&
+                    __hip_atomic_load(a.idle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.idle_limit)) {
           stop = 1.0;
         } else {
           double dt = a.f.dt[s], al = a.f.alpha[s];
@@ -499,7 +595,7 @@ static void launch_fp_kt(bool cell, dim3 g, size_t shm, const FirePArgs &a, cons
 
 int fire_persistent(const ts_batch *b, const ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,
                     const ts_pair_params *pp, int64_t n_iter, void *force, double *energy, double *virial,
-                    int64_t max_atoms, hipStream_t st) {
+                    int64_t max_atoms, bool hand_off, bool *handed_off, hipStream_t st) {
   const int64_t S = b->n_systems;
   NlWork w = nl_work(nl->workspace, b->n_atoms, S);
   FirePArgs a;
@@ -519,6 +615,7 @@ int fire_persistent(const ts_batch *b, const ts_fire_state *fs, const ts_fire_co
   // the work queue and its order live in the fused-loop flag area of the workspace
   a.order = w.flags3;
   a.queue = w.flags3 + 6 * S;
+  a.idle = a.queue + 1;
   a.budget = n_iter;
   hipLaunchKernelGGL(k_fire_order, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, st, S, b->sys_offsets, a.order,
                      a.queue);
@@ -529,7 +626,15 @@ int fire_persistent(const ts_batch *b, const ts_fire_state *fs, const ts_fire_co
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
   }
   const int64_t grid = S < 2 * (int64_t)cus ? S : 2 * (int64_t)cus;
-  const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
+  // hand the tail over once at most a quarter of the chip's workgroups are still iterating: the
+  // slowest systems then run one per compute unit while the rest of the chip idles
+  const int64_t limit = grid - cus / 4;
+  a.idle_limit = (hand_off && limit > 0) ? (int32_t)limit : 0;
+  if (handed_off) *handed_off = a.idle_limit > 0;
+  // positions (3 x float64), wrapped fractional coordinates of the rebuild (float4) and the
+  // rebuild's survivor queues
+  const size_t shm = (size_t)(3 * sizeof(double) + sizeof(float4)) * (size_t)max_atoms +
+                     sizeof(int) * kPSurv * kPW;
   const PairTable t = make_table(pp);
   const dim3 g((unsigned)grid);
   if (pp->prec == TS_PAIR_F32) {

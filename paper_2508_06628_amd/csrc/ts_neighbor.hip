@@ -370,11 +370,71 @@ NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   return w;
 }
 
+// Rebuild list of the small-system path: with force every system, else none yet (flags cleared).
+__global__ void __launch_bounds__(256) k_list_init(int64_t n_sys, int force, int32_t *__restrict__ flags,
+                                                   int32_t *__restrict__ list, int32_t *__restrict__ count) {
+  for (int64_t s = threadIdx.x; s < n_sys; s += blockDim.x) {
+    flags[s] = 0;
+    if (force) list[s] = (int32_t)s;
+  }
+  if (threadIdx.x == 0) *count = force ? (int32_t)n_sys : 0;
+}
+
+// Validity test of every atom; the first atom of a system to exceed the bound appends the system to
+// the rebuild list (a plain read skips the exchange once the flag is visibly set).
+__global__ void k_nl_trigger_list(int64_t n, int64_t stride, const int32_t *__restrict__ sys_idx,
+                                  const double *__restrict__ pos, const double *__restrict__ ref_pos,
+                                  const double *__restrict__ cell, const double *__restrict__ ref_cell,
+                                  int32_t *__restrict__ flags, int32_t *__restrict__ list, int32_t *__restrict__ count,
+                                  double skin, double r_list) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int s = sys_idx[i];
+  double r[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = pos[c * stride + i];
+  if (!list_invalid(r, ref_pos, stride, i, cell + 9 * (int64_t)s, ref_cell + 9 * (int64_t)s, skin, r_list)) return;
+  if (__hip_atomic_load(&flags[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  if (atomicExch(&flags[s], 1) == 0) list[atomicAdd(count, 1)] = s;
+}
+
 int nl_update(const ts_batch *b, ts_neighbor_list *nl, int force, int64_t max_atoms, hipStream_t st) {
   const int64_t n = b->n_atoms, S = b->n_systems, stride = stride_of(b);
   NlWork w = nl_work(nl->workspace, n, S);
   const double r_list = nl->cutoff + nl->skin;
   const unsigned ga = (unsigned)ceil_div(n > 0 ? n : 1, 256);
+  if (max_atoms <= kLdsMaxAtoms) {
+    // systems that fit in LDS: a device list of the systems to rebuild and the row kernel of the
+    // fused step loop (canonical rows straight from a wavefront scan, no sort)
+    int32_t *list = w.flags3 + 3 * S, *count = w.flags3 + 6 * S + 4;
+    hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, st, S, force, w.flags, list, count);
+    TS_LAUNCH_CHECK();
+    if (n == 0) return TS_OK;
+    if (!force) {
+      hipLaunchKernelGGL(k_nl_trigger_list, dim3(ga), dim3(256), 0, st, n, stride, b->system_idx, b->pos,
+                         nl->ref_pos, b->cell, nl->ref_cell, w.flags, list, count, nl->skin, r_list);
+      TS_LAUNCH_CHECK();
+    }
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.offs = b->sys_offsets;
+    a.pos_in = b->pos;
+    a.st_in = stride;
+    a.st_vel = stride;
+    a.cell = b->cell;
+    a.nbr = reinterpret_cast<uint32_t *>(nl->nbr);
+    a.n_nbr = nl->n_nbr;
+    a.max_nbr = nl->max_nbr;
+    a.half = nl->half;
+    a.ref_pos = nl->ref_pos;
+    a.ref_cell = nl->ref_cell;
+    a.status = nl->status;
+    a.r_list = r_list;
+    a.skin = nl->skin;
+    a.list_cur = list;
+    a.count_cur = count;
+    return launch_rebuild(a, S, max_atoms, st);
+  }
   if (!force && n > 0) {
     hipLaunchKernelGGL(k_nl_trigger, dim3(ga), dim3(256), 0, st, n, stride, b->system_idx, b->pos, nl->ref_pos,
                        b->cell, nl->ref_cell, w.flags, nl->skin, r_list);

@@ -98,6 +98,29 @@ __device__ inline bool list_invalid(const double r[3], const double *ref_pos, in
   return bound_exceeded(sqrt(norm2(dlt[0], dlt[1], dlt[2])), strain, skin, r_list);
 }
 
+// Candidate images of one (i, j) pair along one lattice direction: integers S with
+// |f + S| < reach (+ a rounding margin), f the fractional difference.  The range is clipped to
+// |S| <= TS_MAX_IMAGE_SHIFT + 1, so the candidate loops stay short whatever the input (an image
+// at +-16 that is in range is reported by the caller's shift test); a range lying wholly beyond
+// the clip sets *clipped; a non-finite f gives no candidate.
+__device__ inline void image_range(double f, double reach, int *lo, int *hi, bool *clipped) {
+  double l = ceil(-f - reach - 1e-9), h = floor(-f + reach + 1e-9);
+  const double lim = TS_MAX_IMAGE_SHIFT + 1;
+  if (!(l <= h)) {  // empty, or NaN
+    *lo = 0;
+    *hi = -1;
+    return;
+  }
+  if (l > lim || h < -lim) {
+    *clipped = true;
+    *lo = 0;
+    *hi = -1;
+    return;
+  }
+  *lo = (int)fmax(l, -lim);
+  *hi = (int)fmin(h, lim);
+}
+
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st);
 
 // Fills a.chunks / a.rounds / a.n_work for lanes-per-atom tl and the caller's group size (0: from

@@ -276,13 +276,6 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
 constexpr int kRebuildWaves = 8;
 constexpr int kSurvCap = 2 * kWave;  // survivor queue of a wavefront in the wide path
 
-// Candidate images of one (i, j) pair along one lattice direction: integers S with
-// |ds + S| < reach (+ a rounding margin), ds the fractional difference.
-__device__ inline void image_range(double f, double reach, int *lo, int *hi) {
-  *lo = (int)ceil(-f - reach - 1e-9);
-  *hi = (int)floor(-f + reach + 1e-9);
-}
-
 __device__ inline bool shift_ok(int S0, int S1, int S2) {
   // |S| <= 15 for all three: (S + 15) as unsigned is at most 30
   return ((unsigned)(S0 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT) &
@@ -324,6 +317,7 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
                  i20 = (h10 * h21 - h11 * h20) * id, i21 = (h01 * h20 - h00 * h21) * id,
                  i22 = (h00 * h11 - h01 * h10) * id;
     const double vol = fabs(det);
+    if (c0 == 0 && threadIdx.x == 0 && !(isfinite(det) && det != 0.0)) status_raise(a.status, TS_STATUS_NONFINITE, 1);
     // reach_k = r_list / w_k with w_k = V / |a_{k+1} x a_{k+2}|
     const double c0x = h11 * h22 - h12 * h21, c0y = h12 * h20 - h10 * h22, c0z = h10 * h21 - h11 * h20;
     const double c1x = h21 * h02 - h22 * h01, c1y = h22 * h00 - h20 * h02, c1z = h20 * h01 - h21 * h00;
@@ -440,9 +434,9 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
         drx = lx[j] - rx;
         dry = ly[j] - ry;
         drz = lz[j] - rz;
-        image_range(drx * i00 + dry * i10 + drz * i20, re0, &lo0, &hi0);
-        image_range(drx * i01 + dry * i11 + drz * i21, re1, &lo1, &hi1);
-        image_range(drx * i02 + dry * i12 + drz * i22, re2, &lo2, &hi2);
+        image_range(drx * i00 + dry * i10 + drz * i20, re0, &lo0, &hi0, &shift_bad);
+        image_range(drx * i01 + dry * i11 + drz * i21, re1, &lo1, &hi1, &shift_bad);
+        image_range(drx * i02 + dry * i12 + drz * i22, re2, &lo2, &hi2, &shift_bad);
         if (lo0 == hi0 && lo1 == hi1 && lo2 == hi2) {
           // one candidate image (always the case when the cell is wider than 2 r_list)
           const int S0 = lo0, S1 = lo1, S2 = lo2;

@@ -9,7 +9,7 @@ batch (one persistent launch), the soft-sphere jamming batch (FIRE, then NVE), a
 oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--chunk C] [--no-plain] [--no-adjoint] [--no-fire] [--no-cpu]
-    python bench.py --profile-kernels --lanes L     # short launch sequence for rocprofv3
+    python bench.py --profile-kernels --lanes L [--group G]   # short launch sequence for rocprofv3
 """
 from __future__ import annotations
 
@@ -32,7 +32,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes):
+def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes, group=0):
     pot = w.potential
     b = api.Batch.from_workload(w)
     nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
@@ -44,6 +44,7 @@ def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes):
         log(f"autotune: {tune}")
     else:
         nl.lanes_per_atom = lanes
+        nl.group_atoms = group
     F = api.force_buffer(b, w.pair_prec)
     api.ts_pair_forces(b, nl, pp, F)
     chunk = max(1, min(chunk, steps))
@@ -72,7 +73,7 @@ def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes):
         raise RuntimeError(f"neighbor list status after the timed run: {st.tolist()}")
     return dict(ms=ms, wall_s=wall, warmup_steps=w_runs * chunk + rest, rebuilds=int(st[2]),
                 max_nbr=int(st[0]), capacity=nl.max_nbr, batch=b, nl=nl, pp=pp, F=F, lanes=nl.lanes_per_atom,
-                tune=tune)
+                group=nl.group_atoms, tune=tune)
 
 
 def force_kernel_roofline(api, torch, r, reps=200):
@@ -156,14 +157,16 @@ def adjoint_throughput(api, torch, n_systems, n_steps, checkpoint):
                 loss=float(eng.loss.item()), dL_deps=de, dL_dsigma=ds)
 
 
-def fire_copper(api, torch, max_iter=20000):
+def fire_copper(api, torch, max_iter=20000, skin=1.0):
     """Batched FIRE of positions and cell on the uneven 512-system Morse copper batch, in one
-    persistent launch, until every system has max |F| < fmax (and the cell force too)."""
+    persistent launch (its tail handed to the per-iteration kernels), until every system has
+    max |F| < fmax (and the cell force too).  The list skin is a tuning parameter of the relaxation
+    (forces do not depend on it): 1 A trades longer rows for fewer rebuilds under cell changes."""
     from workloads import copper_uneven_batch
     w = copper_uneven_batch(512, seed=2)
     pot = w.potential
     b = api.Batch.from_workload(w)
-    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=2, margin=1.2)
+    nl = api.build_neighbor_list(b, pot.cutoff, skin, bin_factor=2, margin=1.2)
     pp = api.pair_params_from_spec(pot, w.pair_prec)
     cfgd = dict(w.extra["fire"])
     cfgd["relax_cell"] = True
@@ -180,7 +183,8 @@ def fire_copper(api, torch, max_iter=20000):
     ms = e0.elapsed_time(e1)
     it = fs.n_iter.cpu().numpy()
     work = float((it * np.diff(b.h_offsets)).sum())
-    return dict(workload=f"copper_morse_fire_cell_{w.n_systems}_uneven", n_atoms=b.n_atoms, seconds=round(ms * 1e-3, 4),
+    return dict(workload=f"copper_morse_fire_cell_{w.n_systems}_uneven", n_atoms=b.n_atoms, skin_A=skin,
+                seconds=round(ms * 1e-3, 4),
                 converged=int(fs.converged.sum().item()), n_systems=w.n_systems, iterations_mean=round(float(it.mean()), 1),
                 iterations_max=int(it.max()), value=round(work / (ms * 1e-3), 1), unit="atom-iterations/s",
                 list_rebuilds=int(nl.read_status()[2]))
@@ -247,7 +251,7 @@ def cpu_baseline(w, steps=2):
                        f"{dt:.1f} s, single process float64 NumPy")
 
 
-def profile_kernels(api, torch, w, lanes, bin_factor, reps=20, copy_mib=256):
+def profile_kernels(api, torch, w, lanes, bin_factor, reps=20, copy_mib=256, group=0):
     """Fixed launch sequence for rocprofv3 runs (kernel trace and byte counters): the force
     kernel ``reps`` times, two 100-step NVE graph replays, and a plain device copy of
     ``copy_mib`` MiB whose counter readings calibrate the byte counters."""
@@ -255,6 +259,7 @@ def profile_kernels(api, torch, w, lanes, bin_factor, reps=20, copy_mib=256):
     pot = w.potential
     nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
     nl.lanes_per_atom = lanes
+    nl.group_atoms = group
     pp = api.pair_params_from_spec(pot, w.pair_prec)
     F = api.force_buffer(b, w.pair_prec)
     for _ in range(reps):
@@ -279,6 +284,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=100)
     ap.add_argument("--bin-factor", type=int, default=2)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom in the step kernel (0: autotune)")
+    ap.add_argument("--group", type=int, default=0, help="atoms per workgroup in the step kernel (with --lanes)")
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=500)
     ap.add_argument("--no-plain", action="store_true")
@@ -301,9 +307,9 @@ def main():
     w = argon_batch(64, seed=1, n_steps=args.steps)
     log(f"workload {w.name}: {w.n_systems} systems, {w.n_atoms} atoms")
     if args.profile_kernels:
-        print(json.dumps(profile_kernels(api, torch, w, args.lanes or 4, args.bin_factor)), flush=True)
+        print(json.dumps(profile_kernels(api, torch, w, args.lanes or 4, args.bin_factor, group=args.group)), flush=True)
         return
-    r = batched_nve(api, torch, w, args.steps, args.warmup, args.chunk, args.bin_factor, args.lanes)
+    r = batched_nve(api, torch, w, args.steps, args.warmup, args.chunk, args.bin_factor, args.lanes, args.group)
     ms_per_step = r["ms"] / args.steps
     value = w.n_atoms * args.steps / (r["ms"] * 1e-3)
     log(f"batched NVE: {ms_per_step * 1e3:.2f} us/step, {value:.4g} atom-steps/s, rebuilds {r['rebuilds']}")
@@ -325,7 +331,7 @@ def main():
         "config": {"workload": "argon_lj_nve_64x864", "n_systems": w.n_systems, "atoms_per_system": 864,
                    "n_atoms": w.n_atoms, "dt_fs": w.dt, "skin_A": w.skin, "cutoff_A": w.potential.cutoff,
                    "pair_prec": w.pair_prec, "graph_chunk_steps": args.chunk, "bin_factor": args.bin_factor,
-                   "lanes_per_atom": r["lanes"],
+                   "lanes_per_atom": r["lanes"], "group_atoms": r["group"],
                    "list_capacity": r["capacity"], "max_list_len": r["max_nbr"], "system_rebuilds": r["rebuilds"],
                    "wall_s": round(r["wall_s"], 4)},
         "roofline": roof,

@@ -1,10 +1,12 @@
 """Launch-shape autotuner for the batched NVE step loop.
 
 The fused step kernel spreads each atom's neighbor row over ``lanes_per_atom`` lanes of a
-wavefront (1, 2, 4 or 8).  The best value depends on the row length and on how many atoms the
-batch has (few atoms need more lanes per atom to fill 256 CUs).  ``tune_nve`` times a short graph
-replay of the real workload for every candidate on a scratch copy of the state and returns the
-fastest; results are cached on disk per (device architecture, potential, precision, size bucket)
+wavefront (1, 2, 4 or 8), and a workgroup owns ``group_atoms`` atoms of one system (one or more
+rounds of 256 / lanes_per_atom atoms; the system's positions are staged in LDS once per
+workgroup).  The best pair depends on the row length and on how many atoms the batch has (few
+atoms need more lanes per atom to fill 256 CUs; more rounds stage less).  ``tune_nve`` times a
+short graph replay of the real workload for every candidate on a scratch copy of the state and
+returns the fastest; results are cached on disk per (device architecture, potential, precision, size bucket)
 so later runs skip the sweep.  Only timing is done here: every candidate runs the same kernels
 through the C ABI and computes the same trajectory up to float64 summation order.
 """
@@ -20,6 +22,7 @@ import torch
 from . import api
 
 LANE_CHOICES = (1, 2, 4, 8)
+ROUND_CHOICES = (1, 2)  # atom groups per workgroup (group_atoms = rounds * 256 / lanes_per_atom)
 
 
 def cache_path() -> str:
@@ -60,19 +63,22 @@ def key(batch, nl, pp) -> str:
 
 
 def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float, steps: int = 50,
-             reps: int = 3, use_cache: bool = True, choices=LANE_CHOICES) -> dict:
-    """Pick lanes_per_atom for ``ts_nve_step`` on this workload.  Returns
-    {"lanes_per_atom": L, "us_per_step": {L: t, ...}, "cached": bool} and sets it on ``nl``."""
+             reps: int = 3, use_cache: bool = True, choices=LANE_CHOICES, rounds=ROUND_CHOICES) -> dict:
+    """Pick lanes_per_atom and group_atoms for ``ts_nve_step`` on this workload.  Returns
+    {"lanes_per_atom": L, "group_atoms": G, "us_per_step": {"L/G": t, ...}, "cached": bool} and sets
+    both on ``nl``."""
     k = key(batch, nl, pp)
     cache = _load() if use_cache else {}
-    if k in cache:
+    if k in cache and "group_atoms" in cache[k]:
         nl.lanes_per_atom = int(cache[k]["lanes_per_atom"])
+        nl.group_atoms = int(cache[k]["group_atoms"])
         return dict(cache[k], cached=True)
     prec = "f32" if pp.prec == 0 else "f64"
     timings = {}
-    for lanes in choices:
+    cands = [(lanes, r * 256 // lanes) for lanes in choices for r in rounds if not (lanes == 1 and r > 1)]
+    for lanes, group in cands:
         b = batch.clone()
-        trial = api.NeighborList(b, nl.cutoff, nl.skin, nl.max_nbr, nl.bin_factor, nl.half, lanes)
+        trial = api.NeighborList(b, nl.cutoff, nl.skin, nl.max_nbr, nl.bin_factor, nl.half, lanes, group)
         api.ts_neighbor_build(b, trial, force=True)
         F = api.force_buffer(b, prec)
         api.ts_pair_forces(b, trial, pp, F)
@@ -86,15 +92,17 @@ def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float
             e1.record()
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1) * 1e3 / steps)
-        timings[lanes] = round(best, 3)
+        timings[(lanes, group)] = round(best, 3)
         del trial, b, F
     api.ts_release_graphs()
-    lanes = min(timings, key=timings.get)
-    entry = {"lanes_per_atom": int(lanes), "us_per_step": {str(k2): v for k2, v in timings.items()}}
+    lanes, group = min(timings, key=timings.get)
+    entry = {"lanes_per_atom": int(lanes), "group_atoms": int(group),
+             "us_per_step": {f"{l2}/{g2}": v for (l2, g2), v in timings.items()}}
     if use_cache:
         cache[k] = entry
         _store(cache)
     nl.lanes_per_atom = int(lanes)
+    nl.group_atoms = int(group)
     return dict(entry, cached=False)
 
 

@@ -330,28 +330,27 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     // of reach), and the float32 prefilter on wrapped fractional coordinates below is safe
     const bool wide = re0 < 0.5 - 1e-3 && re1 < 0.5 - 1e-3 && re2 < 0.5 - 1e-3;
     __syncthreads();  // the previous chunk's readers are done with lds
+    // LDS: float64 positions [3][ns]; wide cells also float4 wrapped fractional coordinates [ns] and
+    // the wavefronts' survivor queues
     double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
-    float4 *sf = reinterpret_cast<float4 *>(lds);                          // wide: wrapped fractional
-    int *surv = reinterpret_cast<int *>(lds + 2 * ns) + wave * kSurvCap;  // wide: survivor queue
-    if (wide) {
-      for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-        const double x = pin[a0 + k], y = pin[a.st_in + a0 + k], z = pin[2 * a.st_in + a0 + k];
+    float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns);
+    int *surv = reinterpret_cast<int *>(lds + 5 * ns) + wave * kSurvCap;
+    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+      const double x = pin[a0 + k], y = pin[a.st_in + a0 + k], z = pin[2 * a.st_in + a0 + k];
+      lx[k] = x;
+      ly[k] = y;
+      lz[k] = z;
+      if (wide) {
         const double f0 = x * i00 + y * i10 + z * i20, f1 = x * i01 + y * i11 + z * i21,
                      f2 = x * i02 + y * i12 + z * i22;
         sf[k] = make_float4((float)(f0 - floor(f0)), (float)(f1 - floor(f1)), (float)(f2 - floor(f2)), 0.0f);
-      }
-    } else {
-      for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-        lx[k] = pin[a0 + k];
-        ly[k] = pin[a.st_in + a0 + k];
-        lz[k] = pin[2 * a.st_in + a0 + k];
       }
     }
     __syncthreads();
     const int li = c0 + wave;
     if (li >= ns) continue;  // uniform over the wavefront; no block barrier follows before the loop top
     const int64_t i = a0 + li;
-    const double rx = pin[a0 + li], ry = pin[a.st_in + a0 + li], rz = pin[2 * a.st_in + a0 + li];
+    const double rx = lx[li], ry = ly[li], rz = lz[li];
     int cnt = 0;
     bool shift_bad = false;
     if (wide) {
@@ -372,7 +371,7 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
       auto exact = [&](int n) {  // the first n queued survivors
         __builtin_amdgcn_wave_barrier();  // queue writes of other lanes before these reads
         const int j = lane < n ? surv[lane] : li;
-        const double drx = pin[a0 + j] - rx, dry = pin[a.st_in + a0 + j] - ry, drz = pin[2 * a.st_in + a0 + j] - rz;
+        const double drx = lx[j] - rx, dry = ly[j] - ry, drz = lz[j] - rz;
         const double f0 = drx * i00 + dry * i10 + drz * i20, f1 = drx * i01 + dry * i11 + drz * i21,
                      f2 = drx * i02 + dry * i12 + drz * i22;
         // nearest integers without rounding or conversion instructions: t = f + 1.5 2^52 rounds f to
@@ -529,10 +528,8 @@ int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStrea
   const int chunks = (int)ceil_div(max_atoms, kRebuildWaves);
   const int64_t work = n_sys * chunks;
   const unsigned grid = (unsigned)(work < 2048 ? work : 2048);
-  // general path: float64 positions; wide path: float4 fractional coordinates + survivor queues
-  const size_t shm_general = (size_t)3 * sizeof(double) * (size_t)max_atoms;
-  const size_t shm_wide = (size_t)2 * sizeof(double) * (size_t)max_atoms + sizeof(int) * kSurvCap * kRebuildWaves;
-  const size_t shm = shm_general > shm_wide ? shm_general : shm_wide;
+  // float64 positions, float4 fractional coordinates and the survivor queues (wide cells)
+  const size_t shm = (size_t)5 * sizeof(double) * (size_t)max_atoms + sizeof(int) * kSurvCap * kRebuildWaves;
   StepArgs b = a;
   b.n_sys = (int)n_sys;
   hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, b, chunks);

@@ -76,6 +76,28 @@ def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes, group=0)
                 group=nl.group_atoms, tune=tune)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a device copy of known size), or None once the kernel sources have
+    changed since those counters were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_step_argon_64x864_counters.txt")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2508_06628_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    rec = dict(l.split(": ", 1) for l in lines if ": " in l and not l.startswith("#"))
+    if rec.get("csrc_sha256") != h.hexdigest():
+        return None
+    v = rec.get(f"traffic_bytes_per_launch {kernel}")
+    return int(v) if v else None
+
+
 def force_kernel_roofline(api, torch, r, reps=200):
     """Average duration of the pair-force kernel alone, timed with events on the stream it is
     launched on (torch's current stream), and its algorithmic HBM bytes.  For systems that fit the
@@ -102,9 +124,10 @@ def force_kernel_roofline(api, torch, r, reps=200):
     achieved = alg / (avg_ms * 1e-3) / 1e9
     tl = nl.lanes_per_atom if nl.lanes_per_atom > 0 else 4
     ftype = "float" if fbytes == 4 else "double"
+    kernel = f"ts::k_step<0, {ftype}, {tl}, 3>"
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"ts::k_step<0, {ftype}, {tl}, 3>", avg_launch_us=round(avg_ms * 1e3, 3),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kernel),
+                kernel=kernel, avg_launch_us=round(avg_ms * 1e3, 3),
                 launches_timed=reps, alg_bytes_per_launch=alg, alg_bytes_per_atom=round(alg / n, 1),
                 mean_list_len=round(entries / n, 2))
 

@@ -7,7 +7,9 @@
 //     K du = (h - g) (d . du) / r^2 d + g du,
 // and the parameter term is (dg/dtheta)(u_i . d).  Pair arithmetic in the pair precision,
 // accumulators in float64.
+#include "ts_adjoint.h"
 #include "ts_forces.h"
+#include "ts_neighbor.h"
 
 namespace ts {
 
@@ -22,8 +24,25 @@ struct AdjArgs {
   double *lr;        // adj_pos (in/out)
   const double *lv;  // adj_vel (read)
   double *adj_params;
+  double *slots;   // [n_slots][kAdjSlot] partial sums of the parameter gradient
+  int64_t n_slots;
   double w, accel;
 };
+
+// adj_params[k] += sum over the slots of slots[q][k]
+__global__ void k_sum_slots(int64_t n_slots, const double *__restrict__ slots, double *__restrict__ adj_params) {
+  const int k = threadIdx.x;
+  if (k >= kAdjSlot) return;
+  double v = 0.0;
+  for (int64_t q = 0; q < n_slots; ++q) v += slots[(int64_t)kAdjSlot * q + k];
+  adj_params[k] += v;
+}
+
+int launch_sum_slots(int64_t n_slots, const double *slots, double *adj_params, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kAdjSlot), 0, st, n_slots, slots, adj_params);
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
 
 __global__ void k_adj_drift(int64_t n, int64_t st, const double *__restrict__ lr, double *__restrict__ lv, double dt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,17 +119,28 @@ __global__ void __launch_bounds__(256) k_pair_vjp(PairTable tab, AdjArgs a) {
     a.lr[2 * st + i] = a.lr[2 * st + i] + a.w * jz;
   }
   if (a.adj_params) {
+    // workgroup sums go to one of many slots (one word for the whole launch would serialise the
+    // atomics of every wavefront); the caller sums the slots afterwards
+    double *slot = a.slots + (int64_t)kAdjSlot * (blockIdx.x % a.n_slots);
     if (SINGLE) {
+      __shared__ double wsum[256 / kWave][3];
       const double t0 = wave_sum(a.w * tp0), t1 = wave_sum(a.w * tp1), t2 = wave_sum(a.w * tp2);
       if (__lane_id() == 0) {
-        atomicAdd(&a.adj_params[0], t0);
-        atomicAdd(&a.adj_params[1], t1);
-        atomicAdd(&a.adj_params[2], t2);
+        wsum[threadIdx.x / kWave][0] = t0;
+        wsum[threadIdx.x / kWave][1] = t1;
+        wsum[threadIdx.x / kWave][2] = t2;
+      }
+      __syncthreads();
+      if (threadIdx.x < 3) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 256 / kWave; ++q) v += wsum[q][threadIdx.x];
+        atomicAdd(&slot[threadIdx.x], v);
       }
     } else {
       __syncthreads();
-      for (int k = threadIdx.x; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += blockDim.x)
-        if (acc[k] != 0.0) atomicAdd(&a.adj_params[k], acc[k]);
+      for (int k = threadIdx.x; k < kAdjSlot; k += blockDim.x)
+        if (acc[k] != 0.0) atomicAdd(&slot[k], acc[k]);
     }
   }
 }
@@ -329,8 +359,15 @@ extern "C" int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl
   a.lr = adj_pos;
   a.lv = adj_vel;
   a.adj_params = adj_params;
+  const ts::NlWork w = ts::nl_work(nl->workspace, batch->n_atoms, batch->n_systems);
+  a.slots = w.adj_slots;
+  a.n_slots = ts::adj_slot_count(batch->n_systems);
   a.w = w_kick;
   a.accel = accel;
+  if (adj_params) {
+    rc = ts::fill_async<double>(a.slots, ts::kAdjSlot * a.n_slots, 0.0, st);
+    if (rc != TS_OK) return rc;
+  }
   const ts::PairTable t = ts::make_table(pp);
   const bool single = t.n_species == 1 || batch->species == nullptr;
   if (pp->prec == TS_PAIR_F32) {
@@ -343,6 +380,7 @@ extern "C" int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl
     else ts::launch_vjp<TS_SOFT_SPHERE, double>(a, t, single, st);
   }
   TS_LAUNCH_CHECK();
+  if (adj_params) return ts::launch_sum_slots(a.n_slots, a.slots, adj_params, st);
   return TS_OK;
 }
 

@@ -12,6 +12,7 @@
 // flagged-system list as the forward loop) before the next reverse step needs them.
 #include <string>
 
+#include "ts_adjoint.h"
 #include "ts_forces.h"
 #include "ts_graph.h"
 #include "ts_neighbor.h"
@@ -34,7 +35,8 @@ struct AdjStepArgs {
   const double *lr_in, *lv_in;
   double *lr_out, *lv_out;
   int64_t st_in, st_out;
-  double *adj_params;
+  double *adj_params;  // non-null: accumulate the parameter gradient
+  double *slots;       // [S][kAdjSlot] per-system partial sums of the parameter gradient
   double dt_drift, w, accel;
   int32_t *flag_next, *flag_clear, *list_next, *count_next, *count_clear;
   double r_list, skin;
@@ -55,6 +57,7 @@ __global__ void k_list_check(StepArgs a, const double *pos, int64_t n) {
   const double r[3] = {pos[i], pos[n + i], pos[2 * n + i]};
   if (list_invalid(r, a.ref_pos, a.st_vel, i, a.cell + 9 * (int64_t)s, a.ref_cell + 9 * (int64_t)s, a.skin,
                    a.r_list) &&
+      __hip_atomic_load(&a.flag_next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
       atomicExch(&a.flag_next[s], 1) == 0)
     a.list_next[atomicAdd(a.count_next, 1)] = s;
 }
@@ -74,8 +77,11 @@ __global__ void __launch_bounds__(256) k_adj_step(PairTable tab, AdjStepArgs a) 
   const int li = first + grp;
   const bool own = li < ns;
   const int64_t i = a0 + li;
-  table_to_lds(ltab);
-  for (int k = tid; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += 256) acc[k] = 0.0;
+  if (!SINGLE) {
+    table_to_lds(ltab);
+    for (int k = tid; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += 256) acc[k] = 0.0;
+  }
+  const PairCoef pc0 = tab.c[0];  // one species: loop-invariant coefficients in registers
   // stage r_n and the drifted u of the whole system
   double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
   double *ux = lds + 3 * ns, *uy = lds + 4 * ns, *uz = lds + 5 * ns;
@@ -119,7 +125,7 @@ __global__ void __launch_bounds__(256) k_adj_step(PairTable tab, AdjStepArgs a) 
       const double r2 = norm2(dx, dy, dz);
       if (!(r2 < cut2)) return;
       const int sj = SINGLE ? 0 : a.species[a0 + j];
-      const PairCoef &pc = ltab[si * TS_MAX_SPECIES + sj];
+      const PairCoef &pc = SINGLE ? pc0 : ltab[si * TS_MAX_SPECIES + sj];
       if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) return;
       T g, hh;
       pair_g_h<KIND, T>(pc, (T)r2, r2, &g, &hh);
@@ -164,7 +170,10 @@ __global__ void __launch_bounds__(256) k_adj_step(PairTable tab, AdjStepArgs a) 
       // the cell does not change along an NVE trajectory: displacement part of the bound only
       const double dx = a.pos_next[i] - a.ref_pos[i], dy = a.pos_next[a.n + i] - a.ref_pos[a.st + i],
                    dz = a.pos_next[2 * a.n + i] - a.ref_pos[2 * a.st + i];
-      if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list) && atomicExch(&a.flag_next[s], 1) == 0)
+      // (a plain read first: the exchange of every atom over the bound would serialise on one word)
+      if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list) &&
+          __hip_atomic_load(&a.flag_next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+          atomicExch(&a.flag_next[s], 1) == 0)
         a.list_next[atomicAdd(a.count_next, 1)] = s;
     }
   }
@@ -173,17 +182,29 @@ __global__ void __launch_bounds__(256) k_adj_step(PairTable tab, AdjStepArgs a) 
     if (s == 0) *a.count_clear = 0;
   }
   if (a.adj_params) {
+    // workgroup sums go to the system's slot (atomics shared by the workgroups of one system only:
+    // one word for the whole launch would serialise every wavefront of the batch); the slots are
+    // summed into adj_params once per segment
+    double *slot = a.slots + (int64_t)kAdjSlot * s;
     if (SINGLE) {
+      __shared__ double wsum[256 / kWave][3];
       const double v0 = wave_sum(a.w * t0), v1 = wave_sum(a.w * t1), v2 = wave_sum(a.w * t2);
       if ((tid % kWave) == 0) {
-        atomicAdd(&a.adj_params[0], v0);
-        atomicAdd(&a.adj_params[1], v1);
-        atomicAdd(&a.adj_params[2], v2);
+        wsum[tid / kWave][0] = v0;
+        wsum[tid / kWave][1] = v1;
+        wsum[tid / kWave][2] = v2;
+      }
+      __syncthreads();
+      if (tid < 3) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 256 / kWave; ++q) v += wsum[q][tid];
+        atomicAdd(&slot[tid], v);
       }
     } else {
       __syncthreads();
-      for (int k = tid; k < TS_MAX_SPECIES * TS_MAX_SPECIES * 3; k += 256)
-        if (acc[k] != 0.0) atomicAdd(&a.adj_params[k], acc[k]);
+      for (int k = tid; k < kAdjSlot; k += 256)
+        if (acc[k] != 0.0) atomicAdd(&slot[k], acc[k]);
     }
   }
 }
@@ -221,7 +242,9 @@ static int adjoint_segment(const ts_batch *b, ts_neighbor_list *nl, const ts_pai
   const int64_t n = b->n_atoms, S = b->n_systems, sb = stride_of(b);
   NlWork w = nl_work(nl->workspace, n, S);
   const PairTable tab = make_table(pp);
-  const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : 4;
+  // lanes per atom: the list's choice, else 8 for batches too small to fill the chip with 4 (fewer
+  // than 2048 wavefronts), 4 otherwise
+  const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : (n * 4 / kWave < 2048 ? 8 : 4);
   const bool single = tab.n_species == 1 || b->species == nullptr;
   int rc = fill_async<int32_t>(w.flags3, 6 * S + 8, 0, st);
   if (rc != TS_OK) return rc;
@@ -264,7 +287,12 @@ static int adjoint_segment(const ts_batch *b, ts_neighbor_list *nl, const ts_pai
   a.st = sb;
   a.ref_pos = nl->ref_pos;
   a.adj_params = adj_params;
+  a.slots = w.adj_slots;
   a.accel = accel;
+  if (adj_params) {
+    rc = fill_async<double>(w.adj_slots, (int64_t)kAdjSlot * S, 0.0, st);
+    if (rc != TS_OK) return rc;
+  }
   a.r_list = r.r_list;
   a.skin = r.skin;
   for (int p = 0; p < P; ++p) {
@@ -302,6 +330,10 @@ static int adjoint_segment(const ts_batch *b, ts_neighbor_list *nl, const ts_pai
       else launch_adj_kt<TS_SOFT_SPHERE, double>(tl, single, S, max_atoms, a, tab, st);
     }
     TS_LAUNCH_CHECK();
+  }
+  if (adj_params) {
+    rc = launch_sum_slots(S, w.adj_slots, adj_params, st);
+    if (rc != TS_OK) return rc;
   }
   if (P % 2 == 1) {
     // the final state is in the second buffers: copy it to the caller's

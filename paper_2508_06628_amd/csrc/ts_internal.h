@@ -300,37 +300,46 @@ __device__ inline void pair_g_h<TS_SOFT_SPHERE, double>(const PairCoef &pc, doub
   *h = pc.a * pc.c * pc.c;
 }
 
-// Derivatives of g = phi'/r with respect to the raw parameter triple (float64).
+// Derivatives of g = phi'/r with respect to the raw parameter triple (float64).  One division per
+// pair (1/r^2 or 1/r); quotients of the parameters alone are loop invariants for a one-species
+// table and are hoisted by the compiler.
 template <int KIND>
 __device__ inline void pair_dg_dparams(const PairCoef &pc, double r2, double out[3]);
 
 template <>
 __device__ inline void pair_dg_dparams<TS_LJ>(const PairCoef &pc, double r2, double out[3]) {
+  // g = 24 eps / r^2 (s^6 - 2 s^12), s = sigma / r
   const double eps = pc.raw[0], sig = pc.raw[1];
-  const double s2 = sig * sig / r2;
+  const double ir2 = 1.0 / r2;
+  const double s2 = sig * sig * ir2;
   const double sr6 = s2 * s2 * s2;
   const double sr12 = sr6 * sr6;
-  const double g = 24.0 * eps / r2 * (sr6 - 2.0 * sr12);
-  out[0] = g / eps;
-  out[1] = 24.0 * eps / r2 * (6.0 * sr6 - 24.0 * sr12) / sig;
+  out[0] = 24.0 * ir2 * (sr6 - 2.0 * sr12);                    // dg/deps = g / eps
+  out[1] = (24.0 * eps / sig) * ir2 * (6.0 * sr6 - 24.0 * sr12);  // dg/dsigma
   out[2] = 0.0;
 }
 template <>
 __device__ inline void pair_dg_dparams<TS_MORSE>(const PairCoef &pc, double r2, double out[3]) {
+  // g = 2 alpha D (x - x^2) / r, x = exp(-alpha (r - r0))
   const double D = pc.raw[0], al = pc.raw[1], r0 = pc.raw[2];
   const double r = sqrt(r2);
+  const double ir = 1.0 / r;
   const double x = exp(-al * (r - r0));
-  out[0] = 2.0 * al * (x - x * x) / r;
-  out[1] = (2.0 * D * (x - x * x) + 2.0 * al * D * (1.0 - 2.0 * x) * (-(r - r0) * x)) / r;
-  out[2] = 2.0 * al * D * (1.0 - 2.0 * x) * (al * x) / r;
+  const double q = x - x * x, p = 1.0 - 2.0 * x;
+  out[0] = 2.0 * al * q * ir;
+  out[1] = (2.0 * D * q - 2.0 * al * D * p * (r - r0) * x) * ir;
+  out[2] = 2.0 * al * al * D * p * x * ir;
 }
 template <>
 __device__ inline void pair_dg_dparams<TS_SOFT_SPHERE>(const PairCoef &pc, double r2, double out[3]) {
+  // g = -(eps / sigma) (1 - r / sigma) / r
   const double eps = pc.raw[0], sig = pc.raw[1];
+  const double isig = 1.0 / sig;
   const double r = sqrt(r2);
-  const double u = 1.0 - r / sig;
-  out[0] = -u / sig / r;
-  out[1] = (eps / (sig * sig) - 2.0 * eps * r / (sig * sig * sig)) / r;
+  const double ir = 1.0 / r;
+  const double u = 1.0 - r * isig;
+  out[0] = -u * isig * ir;
+  out[1] = eps * isig * isig * (ir - 2.0 * isig);
   out[2] = 0.0;
 }
 

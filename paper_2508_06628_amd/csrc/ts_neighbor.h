@@ -29,8 +29,14 @@ struct NlWork {
   double *pos_alt;    // [3][N] second position buffer of the fused step loop
   double *adj_alt;    // [6][N] second adjoint buffers (positions, velocities) of the reverse loop
   int32_t *flags3;    // fused step loop: rebuild flags [3][S], flagged lists [3][S], counts [3]
+  double *adj_slots;  // [adj_slot_count(S)][kAdjSlot] parameter-gradient partial sums (reverse loop, VJP)
   size_t bytes;
 };
+
+constexpr int kAdjSlot = TS_MAX_SPECIES * TS_MAX_SPECIES * 3;
+// Partial-sum slots of the parameter gradient: one per system, at least 256 (so that workgroups
+// spread over many words even for a single large system).
+inline int64_t adj_slot_count(int64_t n_sys) { return n_sys > 256 ? n_sys : 256; }
 
 NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys);
 

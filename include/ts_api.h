@@ -119,7 +119,7 @@ typedef struct {
   int32_t max_nbr;     /* per-atom capacity (rows of nbr) */
   int32_t bin_factor;  /* cell-list bins per list radius along each direction (1..4) */
   int32_t lanes_per_atom; /* lanes of a wavefront sharing one atom's row in the fused step
-                             kernels: 1, 2, 4 or 8 (0 = 4) */
+                             kernels: 1, 2, 4 or 8 (0 = 8 for batches under 32768 atoms, else 4) */
   int32_t group_atoms;  /* atoms one 256-lane workgroup of the fused step kernels owns (its system's
                            positions are staged in LDS once for all of them): rounded down to a
                            multiple of 256 / lanes_per_atom; 0 = chosen from the batch shape */

@@ -242,9 +242,7 @@ static int adjoint_segment(const ts_batch *b, ts_neighbor_list *nl, const ts_pai
   const int64_t n = b->n_atoms, S = b->n_systems, sb = stride_of(b);
   NlWork w = nl_work(nl->workspace, n, S);
   const PairTable tab = make_table(pp);
-  // lanes per atom: the list's choice, else 8 for batches too small to fill the chip with 4 (fewer
-  // than 2048 wavefronts), 4 otherwise
-  const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : (n * 4 / kWave < 2048 ? 8 : 4);
+  const int tl = lanes_for(nl, n);
   const bool single = tab.n_species == 1 || b->species == nullptr;
   int rc = fill_async<int32_t>(w.flags3, 6 * S + 8, 0, st);
   if (rc != TS_OK) return rc;

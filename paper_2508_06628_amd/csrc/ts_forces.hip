@@ -178,7 +178,7 @@ extern "C" int ts_pair_forces(const ts_batch *batch, const ts_neighbor_list *nl,
     s.max_nbr = nl->max_nbr;
     s.epot = energy;
     s.virial = virial;
-    const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : 4;
+    const int tl = ts::lanes_for(nl, batch->n_atoms);
     const int mode = (energy || virial) ? ts::kStepForceEV : ts::kStepForce;
     return ts::launch_step(mode, tl, nl->group_atoms, s, t, pp->prec, batch->n_systems, max_atoms,
                            batch->h_sys_offsets, st);

@@ -120,7 +120,7 @@ static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const Pai
                               int64_t max_atoms, hipStream_t st, double *traj = nullptr) {
   const int64_t n = b->n_atoms, S = b->n_systems;
   NlWork w = nl_work(nl->workspace, n, S);
-  const int tl = nl->lanes_per_atom > 0 ? nl->lanes_per_atom : 4;
+  const int tl = lanes_for(nl, n);
   int rc = fill_async<int32_t>(w.flags3, 6 * S + 8, 0, st);
   if (rc != TS_OK) return rc;
   if (epot) {

@@ -123,6 +123,13 @@ __device__ inline void image_range(double f, double reach, int *lo, int *hi, boo
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st);
 
+// Lanes per atom of the pair kernels: the list's choice, else 8 for batches too small to fill the
+// chip with 4 (fewer than 2048 wavefronts, i.e. under 32768 atoms), 4 otherwise.
+inline int lanes_for(const ts_neighbor_list *nl, int64_t n_atoms) {
+  if (nl->lanes_per_atom > 0) return nl->lanes_per_atom;
+  return n_atoms * 4 / kWave < 2048 ? 8 : 4;
+}
+
 // Fills a.chunks / a.rounds / a.n_work for lanes-per-atom tl and the caller's group size (0: from
 // the batch shape; h_offs are the host system offsets) and launches the step kernel.
 int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &t, int prec, int64_t n_sys,

@@ -203,13 +203,18 @@ __global__ void __launch_bounds__(256) k_rdf_hist(RdfArgs a, double *g) {
       int b1 = (int)ceil((r + span) / a.dr - 0.5);
       b0 = b0 < 0 ? 0 : b0;
       b1 = b1 > a.n_bins - 1 ? a.n_bins - 1 : b1;
+      // exp(-x_b^2 k) for x_b = x_0 + (b - b0) dr by the exact recurrence e_{b+1} = e_b q_b,
+      // q_{b+1} = q_b c (two exponentials per pair instead of one per bin)
+      const double x0 = (b0 + 0.5) * a.dr - r;
+      double e = exp(-x0 * x0 * inv2s2), q = exp(-(2.0 * x0 * a.dr + a.dr * a.dr) * inv2s2);
+      const double c = exp(-2.0 * a.dr * a.dr * inv2s2);
       for (int b = b0; b <= b1; ++b) {
-        const double x = (b + 0.5) * a.dr - r;
-        const double v = exp(-x * x * inv2s2);
         if (s == s_blk)
-          atomicAdd(&lh[b], v);
+          atomicAdd(&lh[b], e);
         else
-          atomicAdd(&g[(int64_t)s * a.n_bins + b], v);
+          atomicAdd(&g[(int64_t)s * a.n_bins + b], e);
+        e *= q;
+        q *= c;
       }
     }
   }
@@ -264,6 +269,8 @@ __global__ void __launch_bounds__(256) k_rdf_vjp(RdfArgs a, const double *dl_dg,
   const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
   const double invs2 = 1.0 / (a.sigma * a.sigma);
   const double span = 10.0 * a.sigma;
+  const double c = exp(-2.0 * a.dr * a.dr * inv2s2);
+  const double kpref = norm / (4.0 * M_PI * rho * na);  // per-bin weight dg_b kpref / r_b^2
   double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int k = 0; k < nn; ++k) {
     const uint32_t ent = a.nbr[row_index(k, i, st)];
@@ -279,13 +286,18 @@ __global__ void __launch_bounds__(256) k_rdf_vjp(RdfArgs a, const double *dl_dg,
     int b1 = (int)ceil((r + span) / a.dr - 0.5);
     b0 = b0 < 0 ? 0 : b0;
     b1 = b1 > a.n_bins - 1 ? a.n_bins - 1 : b1;
+    // the Gaussian of each bin by the recurrence of k_rdf_hist
     double hs = 0.0;
+    const double x0 = (b0 + 0.5) * a.dr - r;
+    double e = exp(-x0 * x0 * inv2s2), q = exp(-(2.0 * x0 * a.dr + a.dr * a.dr) * inv2s2);
     for (int b = b0; b <= b1; ++b) {
       const double rb = (b + 0.5) * a.dr;
       const double x = rb - r;
-      const double pref = dg[b] * norm / (4.0 * M_PI * rb * rb * rho * na);
-      hs += pref * exp(-x * x * inv2s2) * x * invs2;
+      hs += dg[b] / (rb * rb) * e * x;
+      e *= q;
+      q *= c;
     }
+    hs *= kpref * invs2;
     const double c = -2.0 * hs / r;
     gx += c * dx;
     gy += c * dy;

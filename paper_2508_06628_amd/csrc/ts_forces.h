@@ -18,6 +18,7 @@ struct ForceArgs {
   double *energy;
   double *virial;
   const int32_t *skip;  // per-system flag: leave the system untouched (converged FIRE systems)
+  double *pos4;         // workspace [N][4]: positions packed per atom for the neighbor gathers
 };
 
 ForceArgs make_force_args(const ts_batch *b, const ts_neighbor_list *nl, void *force, double *energy, double *virial,

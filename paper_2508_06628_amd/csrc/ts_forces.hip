@@ -7,15 +7,27 @@
 // float64.  Per-system energy and virial are reduced across the wavefront and added with one
 // float64 atomic per wavefront (lanes of a wavefront almost always share a system).
 #include "ts_forces.h"
+#include "ts_neighbor.h"
 #include "ts_step.h"
 
 namespace ts {
+
+constexpr int kFwdUnroll = 4;  // row entries a thread evaluates together in k_pair_forces
+
+// pos4[i] = (x_i, y_i, z_i, 0): one 32-byte block per atom, so that a neighbor gather touches one
+// cache line instead of one line in each of the three coordinate arrays
+__global__ void k_pack_pos4(int64_t n, int64_t st, const double *__restrict__ pos, double4 *__restrict__ pos4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  pos4[i] = make_double4(pos[i], pos[st + i], pos[2 * st + i], 0.0);
+}
 
 template <int KIND, typename T, bool EV, bool SINGLE>
 __global__ void __launch_bounds__(256) k_pair_forces(PairTable tab, ForceArgs a) {
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   if (!SINGLE) table_to_lds(ltab);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // consecutive atoms (those of one system, whose positions the rows gather) on one XCD's L2
+  const int64_t i = xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   bool valid = i < a.n;
   const int64_t ii = valid ? i : 0;
   const int s = valid ? a.sys_idx[ii] : 0;
@@ -29,29 +41,46 @@ __global__ void __launch_bounds__(256) k_pair_forces(PairTable tab, ForceArgs a)
     const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                  h22 = h[8];
     const double rx = a.pos[ii], ry = a.pos[st + ii], rz = a.pos[2 * st + ii];
-    const int si = (SINGLE || a.species == nullptr) ? 0 : a.species[ii];
+    const bool multi = !SINGLE && a.species != nullptr;  // uniform
+    const int si = multi ? a.species[ii] : 0;
     const int nn = a.n_nbr[ii];
     const double cut2 = tab.cut2;
     const PairCoef pc0 = tab.c[0];
-    for (int k = 0; k < nn; ++k) {
-      const uint32_t ent = a.nbr[row_index(k, ii, st)];
-      const int64_t j = a0 + entry_j(ent);
-      const double S0 = (double)entry_s0(ent), S1 = (double)entry_s1(ent), S2 = (double)entry_s2(ent);
-      const double dx = shift_comp(a.pos[j] - rx, S0, S1, S2, h00, h10, h20);
-      const double dy = shift_comp(a.pos[st + j] - ry, S0, S1, S2, h01, h11, h21);
-      const double dz = shift_comp(a.pos[2 * st + j] - rz, S0, S1, S2, h02, h12, h22);
-      const double r2 = norm2(dx, dy, dz);
-      if (!(r2 < cut2)) continue;
-      const PairCoef &pc = (SINGLE || a.species == nullptr) ? pc0 : ltab[si * TS_MAX_SPECIES + a.species[j]];
-      if (KIND == TS_SOFT_SPHERE && !(r2 < pc.sig2)) continue;
-      T phi = (T)0;
-      const double g = (double)pair_g<KIND, T>(pc, (T)r2, r2, &phi, EV);
-      acc_force(g, dx, dy, dz, fx, fy, fz);
-      if (EV) {
-        e += (double)phi;
-        acc_virial(g, dx, dy, dz, w);
+    // kFwdUnroll entries at a time: their neighbor loads are issued together and the pairs are
+    // evaluated without branches (entries past the row end or beyond the cutoff add exact zeros,
+    // so the sums round as in a plain loop over the in-range pairs)
+    for_row_batched<1, kFwdUnroll>(a.nbr, st, ii, nn, 0, [&](const uint32_t *ent, const bool *ok) {
+      double xj[kFwdUnroll], yj[kFwdUnroll], zj[kFwdUnroll];
+      int sj[kFwdUnroll];
+#pragma unroll
+      for (int u = 0; u < kFwdUnroll; ++u) {
+        const int64_t j = ok[u] ? a0 + entry_j(ent[u]) : ii;  // masked visits read atom i itself
+        const double4 pj = reinterpret_cast<const double4 *>(a.pos4)[j];
+        xj[u] = pj.x;
+        yj[u] = pj.y;
+        zj[u] = pj.z;
+        sj[u] = multi ? a.species[j] : 0;
       }
-    }
+#pragma unroll
+      for (int u = 0; u < kFwdUnroll; ++u) {
+        const double S0 = (double)entry_s0(ent[u]), S1 = (double)entry_s1(ent[u]), S2 = (double)entry_s2(ent[u]);
+        const double dx = shift_comp(xj[u] - rx, S0, S1, S2, h00, h10, h20);
+        const double dy = shift_comp(yj[u] - ry, S0, S1, S2, h01, h11, h21);
+        const double dz = shift_comp(zj[u] - rz, S0, S1, S2, h02, h12, h22);
+        const double r2 = norm2(dx, dy, dz);
+        const PairCoef &pc = multi ? ltab[si * TS_MAX_SPECIES + sj[u]] : pc0;
+        bool in = ok[u] && r2 < cut2;
+        if (KIND == TS_SOFT_SPHERE) in = in && r2 < pc.sig2;
+        T phi = (T)0;
+        const T gt = pair_g<KIND, T>(pc, (T)r2, r2, &phi, EV);
+        const double g = in ? (double)gt : 0.0;
+        acc_force(g, dx, dy, dz, fx, fy, fz);
+        if (EV) {
+          e += in ? (double)phi : 0.0;
+          acc_virial(g, dx, dy, dz, w);
+        }
+      }
+    });
     T *F = static_cast<T *>(a.force);
     F[ii] = (T)fx;
     F[st + ii] = (T)fy;
@@ -101,7 +130,10 @@ int launch_forces(const ForceArgs &a, int64_t n_sys, const PairTable &t, int pre
     TS_LAUNCH_CHECK();
   }
   if (a.n == 0) return TS_OK;
-  const dim3 g((unsigned)ceil_div(a.n, 256));
+  hipLaunchKernelGGL(k_pack_pos4, dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, st, a.n, a.stride, a.pos,
+                     reinterpret_cast<double4 *>(a.pos4));
+  TS_LAUNCH_CHECK();
+  const dim3 g((unsigned)(ceil_div(ceil_div(a.n, 256), kXcds) * kXcds));  // a multiple of kXcds for xcd_order
   const bool single = t.n_species == 1 || a.species == nullptr;
   const bool do_ev = ev && (a.energy || a.virial);
   if (prec == TS_PAIR_F32) {
@@ -133,6 +165,7 @@ ForceArgs make_force_args(const ts_batch *b, const ts_neighbor_list *nl, void *f
   a.energy = energy;
   a.virial = virial;
   a.skip = skip;
+  a.pos4 = nl_work(nl->workspace, b->n_atoms, b->n_systems).pos4;
   return a;
 }
 

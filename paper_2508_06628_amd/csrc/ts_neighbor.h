@@ -29,6 +29,7 @@ struct NlWork {
   double *pos_alt;    // [3][N] second position buffer of the fused step loop
   double *adj_alt;    // [6][N] second adjoint buffers (positions, velocities) of the reverse loop
   int32_t *flags3;    // fused step loop: rebuild flags [3][S], flagged lists [3][S], counts [3]
+  double *pos4;       // [N][4] positions packed per atom (x, y, z, unused) for neighbor gathers
   double *adj_slots;  // [adj_slot_count(S)][kAdjSlot] parameter-gradient partial sums (reverse loop, VJP)
   size_t bytes;
 };

@@ -366,6 +366,7 @@ NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   w.pos_alt = reinterpret_cast<double *>(take(24 * (n_atoms + 1)));
   w.adj_alt = reinterpret_cast<double *>(take(48 * (n_atoms + 1)));
   w.flags3 = reinterpret_cast<int32_t *>(take(4 * (6 * n_sys + 8)));
+  w.pos4 = reinterpret_cast<double *>(take(32 * (n_atoms + 1)));
   w.adj_slots = reinterpret_cast<double *>(take(sizeof(double) * kAdjSlot * adj_slot_count(n_sys)));
   w.bytes = static_cast<size_t>(p - static_cast<char *>(ws));
   return w;

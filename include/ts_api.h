@@ -181,6 +181,24 @@ int ts_nve_step(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_param
 int ts_nve_record(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_params *pp, double dt, double accel,
                   int32_t n_steps, void *force, double *traj, int32_t use_graph, ts_stream_t stream);
 
+/* n_steps of Langevin (NVT) dynamics, the integrator of the paper's batched MD benchmark
+   (Section 4), as the BAOAB splitting (Leimkuhler and Matthews 2013; the paper names no scheme):
+     v += dt/2 a F/m;  r += dt/2 v;  v = c1 v + sqrt((1 - c1^2) a kT_s / m) xi;  r += dt/2 v;
+     [list update];  F = F(r);  v += dt/2 a F/m,        c1 = exp(-gamma dt),
+   a = accel as in ts_nve_step, gamma >= 0 the friction (1/time), kT device [S] the per-system
+   temperature in energy units.  The normals xi of atom i at step t come from the counter-based
+   generator Philox4x32-10 (Salmon et al., SC 2011) with key (seed low word, seed high word) and
+   counter (i, t low word, t high word, 0): uniforms (x_k + 1/2) 2^-32, Box-Muller pairs
+   (u0, u1) -> x, y and (u2, u3) -> z (cosine branch).  rng_step: device uint64 counter t of the
+   first step, advanced by n_steps by the call (so a cached graph replays new numbers).
+   force: in F(r_0), out F(r_n), as ts_nve_step.  gamma = 0 gives velocity Verlet (with the drift
+   in two halves).  Graph caching as ts_nve_step (the key holds seed and gamma, not the counter).
+   Errors: TS_E_INVALID (dt, accel not finite/positive, gamma negative or not finite, kT or
+   rng_step NULL, n_steps < 0, vel NULL, more than 2^32 atoms), TS_E_UNSUPPORTED, TS_E_HIP. */
+int ts_langevin_step(const ts_batch *batch, ts_neighbor_list *nl, const ts_pair_params *pp, double dt, double accel,
+                     double gamma, const double *kT, uint64_t seed, uint64_t *rng_step, int32_t n_steps, void *force,
+                     int32_t use_graph, ts_stream_t stream);
+
 /* FIRE relaxation (Bitzek et al., PRL 97, 170201 (2006); the paper's structural relaxation
    optimizers, Abstract).  Per system and iteration: forces; stop if converged
    (max_i |F_i| < fmax, and with relax_cell also max |G_ab| < fmax); from the second iteration on

@@ -123,6 +123,9 @@ SIGNATURES = {
                               c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "ts_nve_record": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double,
                                 c_double, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "ts_langevin_step": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double,
+                                   c_double, c_double, c_void_p, ctypes.c_uint64, c_void_p, c_int32, c_void_p, c_int32,
+                                   c_void_p]),
     "ts_adjoint_segment": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_void_p,
                                      c_int32, c_double, c_double, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                                      c_int32, c_void_p]),

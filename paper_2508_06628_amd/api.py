@@ -264,6 +264,15 @@ def ts_nve_step(batch, nl, pp, dt, accel, n_steps, force, epot=None, ekin=None, 
                                                       1 if use_graph else 0, _stream(stream)))
 
 
+def ts_langevin_step(batch, nl, pp, dt, accel, gamma, kT, seed, rng_step, n_steps, force, use_graph=True,
+                     stream=None):
+    """BAOAB Langevin steps; kT: device float64 [S]; rng_step: device int64 [1] step counter (advanced)."""
+    return N.check("ts_langevin_step", N.lib().ts_langevin_step(
+        ctypes.byref(batch.struct()), ctypes.byref(nl.struct()), ctypes.byref(pp), float(dt), float(accel),
+        float(gamma), _p(kT), int(seed) & 0xFFFFFFFFFFFFFFFF, _p(rng_step), int(n_steps), _p(force),
+        1 if use_graph else 0, _stream(stream)))
+
+
 def ts_nve_record(batch, nl, pp, dt, accel, n_steps, force, traj, use_graph=True, stream=None):
     return N.check("ts_nve_record", N.lib().ts_nve_record(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
                                                           ctypes.byref(pp), float(dt), float(accel), int(n_steps),

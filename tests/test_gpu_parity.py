@@ -379,3 +379,35 @@ def test_fused_lists_match_oracle_at_reference_positions(lanes):
     assert_forces_close(F.T.double().cpu().numpy(), F_ref, A, 1e-5)
     assert np.all(np.abs(E.cpu().numpy() - E_ref) <= 1e-6 * se)
     assert np.all(np.abs(W.cpu().numpy().reshape(-1, 3, 3) - W_ref).max(axis=(1, 2)) <= 1e-6 * sw)
+
+
+# ----------------------------------------------------------------------------- Langevin
+
+
+def test_langevin_matches_oracle():
+    # BAOAB steps with the per-atom Philox normals: same counters on both sides, so the trajectories
+    # agree to float64 rounding; two calls continue the counter, eager and graph runs are identical
+    from oracle import langevin as olang
+    api = _api()
+    w = argon_batch(2, seed=17, reps=(3, 3, 3))
+    pot = w.potential
+    kT = np.array([0.02, 0.035])  # eV
+    gamma, seed, K, t0 = 0.01, 123456789012345, 12, 5  # gamma in 1/fs
+    ref = olang.baoab(w.pos, w.vel, w.mass, w.cell, w.sys_offsets, w.species, pot, w.dt, K, w.accel, gamma, kT,
+                      seed, step0=t0)
+    runs = []
+    for use_graph in (True, False):
+        b = _batch(w)
+        nl = api.build_neighbor_list(b, pot.cutoff, w.skin)
+        pp = api.pair_params_from_spec(pot, "f64")
+        F, _, _ = api.compute_forces(b, nl, pp, "f64")
+        kTd = torch.tensor(kT, device="cuda")
+        ctr = torch.tensor([t0], dtype=torch.int64, device="cuda")
+        api.ts_langevin_step(b, nl, pp, w.dt, w.accel, gamma, kTd, seed, ctr, K // 2, F, use_graph=use_graph)
+        api.ts_langevin_step(b, nl, pp, w.dt, w.accel, gamma, kTd, seed, ctr, K - K // 2, F, use_graph=use_graph)
+        torch.cuda.synchronize()
+        assert int(ctr.item()) == t0 + K
+        runs.append((b.positions(), b.velocities()))
+        assert np.abs(runs[-1][0] - ref["pos"]).max() <= 1e-9
+        assert np.abs(runs[-1][1] - ref["vel"]).max() <= 1e-9 * np.abs(ref["vel"]).max()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])

@@ -76,6 +76,37 @@ def batched_nve(api, torch, w, steps, warmup, chunk, bin_factor, lanes, group=0)
                 group=nl.group_atoms, tune=tune)
 
 
+def langevin_throughput(api, torch, w, steps, chunk, bin_factor, gamma=0.01, temp_k=85.0):
+    """BAOAB Langevin on the same batch, in graph-replayed calls of `chunk` steps."""
+    pot = w.potential
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
+    pp = api.pair_params_from_spec(pot, w.pair_prec)
+    F = api.force_buffer(b, w.pair_prec)
+    api.ts_pair_forces(b, nl, pp, F)
+    k_b = 8.617333262145179e-5  # eV/K
+    kT = torch.full((w.n_systems,), k_b * temp_k, dtype=torch.float64, device="cuda")
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chunk = max(1, min(chunk, steps))
+    n_full = max(1, steps // chunk)
+    api.ts_langevin_step(b, nl, pp, w.dt, w.accel, gamma, kT, 2024, ctr, chunk, F)  # instantiate the graph
+    torch.cuda.synchronize()
+    nl.status.zero_()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(n_full):
+        api.ts_langevin_step(b, nl, pp, w.dt, w.accel, gamma, kT, 2024, ctr, chunk, F)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    st = nl.read_status()
+    if st[1] or st[3] or st[4]:
+        raise RuntimeError(f"neighbor list status after the Langevin run: {st.tolist()}")
+    n = n_full * chunk
+    return dict(value=round(w.n_atoms * n / (ms * 1e-3), 1), unit="atom-steps/s", steps=n,
+                us_per_step=round(ms * 1e3 / n, 2), gamma_per_fs=gamma, temperature_K=temp_k, rebuilds=int(st[2]))
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary (FETCH_SIZE +
     WRITE_SIZE, scaled by a device copy of known size), or None once the kernel sources have
@@ -312,6 +343,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=500)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-langevin", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fire", action="store_true", help="skip the copper FIRE and soft-sphere workloads")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -364,6 +396,9 @@ def main():
         p["speedup_batched_vs_plain"] = round(value / p["value"], 2)
         out["plain_path"] = p
         log(f"plain path: {p['value']:.4g} atom-steps/s")
+    if not args.no_langevin:
+        out["langevin"] = langevin_throughput(api, torch, w, args.steps, args.chunk, args.bin_factor)
+        log(f"langevin: {out['langevin']}")
     if not args.no_adjoint:
         a = adjoint_throughput(api, torch, 16, args.adjoint_steps, 50)
         out["adjoint"] = a

@@ -1,45 +1,17 @@
 // Langevin (NVT) dynamics over the whole batch: BAOAB splitting with one force evaluation per
 // step; the normals come from Philox4x32-10, a counter-based generator, so that every atom and
-// step has its own reproducible draw without generator state in memory.
+// step has its own reproducible draw without generator state in memory.  Batches whose systems fit
+// in LDS run the fused step kernel (the O step in its drift); others run the per-atom kernels below
+// around the general force kernel.
 #include <string>
 
 #include "ts_forces.h"
 #include "ts_graph.h"
 #include "ts_neighbor.h"
+#include "ts_rng.h"
+#include "ts_step.h"
 
 namespace ts {
-
-// Ten rounds of Philox4x32 (Salmon et al., SC 2011) on the counter c with the key (k0, k1).
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-  constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;  // round multipliers
-  constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;  // key increments
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(kM0, c[0]), lo0 = kM0 * c[0];
-    const uint32_t hi1 = __umulhi(kM1, c[2]), lo1 = kM1 * c[2];
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += kW0;
-    k1 += kW1;
-  }
-}
-
-// Standard normals of atom i at step t: Box-Muller on the four uniforms (x + 1/2) 2^-32.
-__device__ inline void atom_normals(uint64_t i, uint64_t t, uint32_t key0, uint32_t key1, double z[3]) {
-  uint32_t c[4] = {(uint32_t)i, (uint32_t)t, (uint32_t)(t >> 32), 0u};
-  philox4x32_10(c, key0, key1);
-  double u[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) u[k] = ((double)c[k] + 0.5) * 0x1p-32;
-  const double r0 = sqrt(-2.0 * log(u[0])), r2 = sqrt(-2.0 * log(u[2]));
-  const double t1 = 2.0 * M_PI * u[1], t3 = 2.0 * M_PI * u[3];
-  z[0] = r0 * cos(t1);
-  z[1] = r0 * sin(t1);
-  z[2] = r2 * cos(t3);
-}
 
 // B A O A of step k of the call: v += dt/2 a F/m; r += dt/2 v; v = c1 v + c2 sqrt(a kT_s / m) xi;
 // r += dt/2 v.  From the second step of a call on, the closing B of the previous step (the same
@@ -51,9 +23,8 @@ __global__ void k_lang_baoa(int64_t n, int64_t st, const int32_t *__restrict__ s
                             uint32_t key0, uint32_t key1, const uint64_t *__restrict__ rng_step, int k) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double m = mass ? mass[i] : 1.0;
-  const double sc = mass ? accel / m : accel;
-  const double sd = c2 * sqrt(accel * kT[sys_idx[i]] / m);
+  const double sc = mass ? accel / mass[i] : accel;
+  const double sd = c2 * sqrt(kT[sys_idx[i]] * sc);
   double z[3];
   atom_normals((uint64_t)i, *rng_step + (uint64_t)k, key0, key1, z);
 #pragma unroll
@@ -92,6 +63,11 @@ static int langevin_sequence(const ts_batch *b, ts_neighbor_list *nl, const Pair
   const double c1 = std::exp(-gamma * dt), c2 = std::sqrt(1.0 - c1 * c1);
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
   const T *F = static_cast<const T *>(force);
+  if (n_steps >= 1 && n > 0 && max_atoms <= kLdsMaxAtoms && !nl->half && fused_enabled()) {
+    const LangParams lp{kT, c1, c2, key0, key1, rng_step};
+    return nve_fused_sequence(b, nl, tab, prec, dt, accel, n_steps, force, nullptr, nullptr, nullptr, max_atoms, st,
+                              nullptr, &lp);
+  }
   for (int k = 0; k < n_steps; ++k) {
     if (n > 0) {
       hipLaunchKernelGGL(k_lang_baoa<T>, g, dim3(256), 0, st, n, s_, b->system_idx, b->pos, b->vel, F, b->mass, kT,
@@ -135,6 +111,7 @@ extern "C" int ts_langevin_step(const ts_batch *batch, ts_neighbor_list *nl, con
   ts::key_add(key, n_steps);
   ts::key_add(key, max_atoms);
   ts::key_add(key, force);
+  ts::key_add(key, ts::fused_enabled());
   const ts::PairTable tab = ts::make_table(pp);
   return ts::run_graph_cached(use_graph != 0, key, ts::as_stream(stream), [&](hipStream_t s) {
     if (pp->prec == TS_PAIR_F32)

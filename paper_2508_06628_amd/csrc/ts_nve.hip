@@ -12,7 +12,7 @@
 namespace ts {
 
 // TS_NVE_UNFUSED=1 selects the multi-kernel step (separate list update, force and kick launches)
-// instead of the fused one; both compute the same trajectory.
+// instead of the fused one; both compute the same trajectory up to rounding.
 bool fused_enabled() {
   const char *e = std::getenv("TS_NVE_UNFUSED");
   return !(e && e[0] == '1');
@@ -115,9 +115,9 @@ static int nve_sequence_t(const ts_batch *b, ts_neighbor_list *nl, const PairTab
 // One launch per step (see ts_step.hip): systems of at most kLdsMaxAtoms atoms, full list.
 // With traj != null every position r_0..r_N is written to traj ([N+1][3][n_atoms]), which then
 // serves as the ping-pong position storage of the loop.
-static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable &tab, int prec, double dt,
-                              double accel, int n_steps, void *force, double *epot, double *ekin, double *virial,
-                              int64_t max_atoms, hipStream_t st, double *traj = nullptr) {
+int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable &tab, int prec, double dt,
+                       double accel, int n_steps, void *force, double *epot, double *ekin, double *virial,
+                       int64_t max_atoms, hipStream_t st, double *traj, const LangParams *lang) {
   const int64_t n = b->n_atoms, S = b->n_systems;
   NlWork w = nl_work(nl->workspace, n, S);
   const int tl = lanes_for(nl, n);
@@ -154,8 +154,14 @@ static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const Pai
   a.half_dt = 0.5 * dt;
   a.dt = dt;
   a.accel = accel;
+  if (lang) {
+    a.lang = *lang;
+    a.lang_adv = n_steps;
+  }
   for (int step = 0; step <= n_steps; ++step) {
-    const int mode = step == 0 ? kStepFirst : (step == n_steps ? kStepLast : kStepMid);
+    const int mode = step == 0 ? (lang ? kStepLangFirst : kStepFirst)
+                               : (step == n_steps ? kStepLast : (lang ? kStepLangMid : kStepMid));
+    a.lang_k = step;
     a.pos_in = buf[step % 2];
     a.st_in = sts[step % 2];
     a.pos_out = buf[(step + 1) % 2];
@@ -181,7 +187,7 @@ static int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const Pai
     }
     a.epot = mode == kStepLast ? epot : nullptr;
     a.virial = mode == kStepLast ? virial : nullptr;
-    if (mode != kStepFirst) {
+    if (step != 0) {
       rc = launch_rebuild(a, S, max_atoms, st);
       if (rc != TS_OK) return rc;
     }

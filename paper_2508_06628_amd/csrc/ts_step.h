@@ -2,6 +2,7 @@
 #pragma once
 
 #include "ts_internal.h"
+#include "ts_rng.h"
 
 namespace ts {
 
@@ -10,6 +11,8 @@ constexpr int kStepMid = 1;    // forces, two half kicks, drift, validity test
 constexpr int kStepLast = 2;   // forces (+ energy, virial), last half kick
 constexpr int kStepForce = 3;  // forces only (ts_pair_forces)
 constexpr int kStepForceEV = 4;  // forces, energy and virial (ts_pair_forces)
+constexpr int kStepLangFirst = 5;  // Langevin: first half kick, half drift, O step, half drift
+constexpr int kStepLangMid = 6;    // Langevin: forces, two half kicks, half drift, O step, half drift, validity
 constexpr int kStepThreads = 256;  // workgroup size of the step kernel
 constexpr int kStepUnroll = 4;      // row entries a lane evaluates together in the step kernel
 constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)
@@ -46,6 +49,11 @@ struct StepArgs {
   int rounds;
   int64_t n_work;  // n_systems * chunks (the grid is n_work rounded up to a multiple of kXcds)
   int n_sys;       // systems in the batch (rebuild launch)
+  // Langevin modes: O step of this launch (step index lang_k of the call) and, with a non-null
+  // rng_step, the counter advance by lang_adv done by the call's last launch
+  LangParams lang;
+  int lang_k;
+  int lang_adv;
 };
 
 // Target number of non-empty workgroups of a step launch when the caller leaves the grouping open.
@@ -134,5 +142,15 @@ inline int lanes_for(const ts_neighbor_list *nl, int64_t n_atoms) {
 // the batch shape; h_offs are the host system offsets) and launches the step kernel.
 int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &t, int prec, int64_t n_sys,
                 int64_t max_atoms, const int64_t *h_offs, hipStream_t st);
+
+// TS_NVE_UNFUSED=1 in the environment selects the multi-kernel step loops instead of the fused one.
+bool fused_enabled();
+
+// Fused step loop (k_rebuild_rows + k_step per step) over a batch whose systems fit in LDS, full
+// list.  With traj != null every position r_0..r_N is written to traj ([N+1][3][n_atoms]); with
+// lang != null the steps are BAOAB Langevin steps instead of velocity-Verlet ones.
+int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable &tab, int prec, double dt,
+                       double accel, int n_steps, void *force, double *epot, double *ekin, double *virial,
+                       int64_t max_atoms, hipStream_t st, double *traj = nullptr, const LangParams *lang = nullptr);
 
 }  // namespace ts

@@ -10,7 +10,8 @@
 //   one system (TL lanes per atom); it stages the system's positions r_n in LDS once, evaluates the
 //   pair forces of its atoms (TL lanes per atom, reduced across lanes), applies the two half kicks that meet at step n and the drift to r_{n+1}
 //   (written to the other position buffer) and tests the list validity bound for r_{n+1}, appending
-//   the system to the next rebuild list when it is exceeded.
+//   the system to the next rebuild list when it is exceeded.  The Langevin modes replace the drift
+//   by half drift, O step (per-atom Philox normals), half drift: a BAOAB step.
 // Systems never exchange data, so no synchronisation between workgroups is needed beyond the
 // kernel boundaries.
 #include "ts_forces.h"
@@ -32,6 +33,11 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   extern __shared__ double lds[];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   constexpr int APB = kStepThreads / TL;
+  constexpr bool LANG = MODE == kStepLangFirst || MODE == kStepLangMid;
+  constexpr bool MID = MODE == kStepMid || MODE == kStepLangMid;
+  // Langevin: no launch after the call's last one reads the counter of this call
+  if (MODE == kStepLast && a.lang.rng_step && blockIdx.x == 0 && threadIdx.x == 0)
+    *a.lang.rng_step += (uint64_t)a.lang_adv;
   const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
   if (wg >= a.n_work) return;
   // uniform values: keep them in scalar registers (a vector division result would drag every
@@ -46,22 +52,33 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   const int grp = tid / TL, lane = tid % TL;
   const double *h = a.cell + 9 * (int64_t)s;
 
-  if (MODE == kStepFirst) {
-    // v += dt/2 a F(r_0); r_1 = r_0 + dt v; list validity of r_1 (cell change included)
+  if (MODE == kStepFirst || MODE == kStepLangFirst) {
+    // v += dt/2 a F(r_0); r_1 = r_0 + dt v (Langevin: r += dt/2 v, O step, r += dt/2 v); list
+    // validity of r_1 (cell change included)
+    const double kT = LANG ? a.lang.kT[s] : 0.0;
+    const uint64_t t = LANG ? *a.lang.rng_step + (uint64_t)a.lang_k : 0;
     for (int r = 0; r < a.rounds; ++r) {
       const int li = first + r * APB + grp;
       if (!(li < ns && lane == 0)) continue;
       const int64_t i = a0 + li;
       const T *F = static_cast<const T *>(a.force);
       const double sc = a.mass ? a.accel / a.mass[i] : a.accel;
-      double rn[3];
+      double rn[3], z[3] = {0.0, 0.0, 0.0};
+      if (LANG) atom_normals((uint64_t)i, t, a.lang.key0, a.lang.key1, z);
+      const double sd = LANG ? a.lang.c2 * sqrt(kT * sc) : 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double v = fma(a.half_dt * (double)F[c * a.st_vel + i], sc, a.vel[c * a.st_vel + i]);
-        a.vel[c * a.st_vel + i] = v;
+        double v = fma(a.half_dt * (double)F[c * a.st_vel + i], sc, a.vel[c * a.st_vel + i]);
         const double r0 = a.pos_in[c * a.st_in + i];
         if (a.pos_copy) a.pos_copy[c * a.n_atoms + i] = r0;
-        rn[c] = fma(a.dt, v, r0);
+        if (LANG) {
+          const double rh = fma(a.half_dt, v, r0);
+          v = fma(a.lang.c1, v, sd * z[c]);
+          rn[c] = fma(a.half_dt, v, rh);
+        } else {
+          rn[c] = fma(a.dt, v, r0);
+        }
+        a.vel[c * a.st_vel + i] = v;
         a.pos_out[c * a.st_out + i] = rn[c];
       }
       if (list_invalid(rn, a.ref_pos, a.st_vel, i, h, a.ref_cell + 9 * (int64_t)s, a.skin, a.r_list))
@@ -89,7 +106,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
 #pragma unroll
       for (int c = 0; c < 3; ++c) pre.v[c] = a.vel[c * st + i];
       pre.sc = a.mass ? a.accel / a.mass[i] : a.accel;
-      if (MODE == kStepMid) {
+      if (MID) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) pre.ref[c] = a.ref_pos[c * st + i];
       }
@@ -109,6 +126,8 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
 
   // 3. pair forces of this block's atoms, TL lanes per atom
   constexpr bool EV = MODE == kStepLast || MODE == kStepForceEV;
+  const double lang_kT = LANG ? a.lang.kT[s] : 0.0;
+  const uint64_t lang_t = LANG ? *a.lang.rng_step + (uint64_t)a.lang_k : 0;
   double e = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // over all rounds
   for (int r = 0; r < a.rounds; ++r) {
     const int base = first + r * APB;
@@ -214,11 +233,28 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
         F[i] = Fx;
         F[st + i] = Fy;
         F[2 * st + i] = Fz;
-      } else if (MODE == kStepMid) {
+      } else if (MID) {
         vx = fma(hx, sc, vx);
         vy = fma(hy, sc, vy);
         vz = fma(hz, sc, vz);
-        const double nx = fma(a.dt, vx, rx), ny = fma(a.dt, vy, ry), nz = fma(a.dt, vz, rz);
+        double nx, ny, nz;
+        if (LANG) {
+          // r += dt/2 v; v = c1 v + c2 sqrt(a kT_s / m) xi; r += dt/2 v
+          double z[3];
+          atom_normals((uint64_t)i, lang_t, a.lang.key0, a.lang.key1, z);
+          const double sd = a.lang.c2 * sqrt(lang_kT * sc);
+          const double ax = fma(a.half_dt, vx, rx), ay = fma(a.half_dt, vy, ry), az = fma(a.half_dt, vz, rz);
+          vx = fma(a.lang.c1, vx, sd * z[0]);
+          vy = fma(a.lang.c1, vy, sd * z[1]);
+          vz = fma(a.lang.c1, vz, sd * z[2]);
+          nx = fma(a.half_dt, vx, ax);
+          ny = fma(a.half_dt, vy, ay);
+          nz = fma(a.half_dt, vz, az);
+        } else {
+          nx = fma(a.dt, vx, rx);
+          ny = fma(a.dt, vy, ry);
+          nz = fma(a.dt, vz, rz);
+        }
         a.pos_out[i] = nx;
         a.pos_out[a.st_out + i] = ny;
         a.pos_out[2 * a.st_out + i] = nz;
@@ -244,7 +280,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
       }
     }
   }  // rounds
-  if (MODE == kStepMid && chunk == 0 && tid == 0) {
+  if (MID && chunk == 0 && tid == 0) {
     a.flag_clear[s] = 0;
     if (s == 0) *a.count_clear = 0;
   }
@@ -541,6 +577,10 @@ template <int KIND, typename T, int TL>
 static void launch_step_k(int mode, const StepArgs &a, const PairTable &t, dim3 g, size_t shm, hipStream_t st) {
   if (mode == kStepFirst)
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepFirst>), g, dim3(kStepThreads), 0, st, t, a);
+  else if (mode == kStepLangFirst)
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLangFirst>), g, dim3(kStepThreads), 0, st, t, a);
+  else if (mode == kStepLangMid)
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLangMid>), g, dim3(kStepThreads), shm, st, t, a);
   else if (mode == kStepMid)
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepMid>), g, dim3(kStepThreads), shm, st, t, a);
   else if (mode == kStepLast)

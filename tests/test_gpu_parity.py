@@ -384,9 +384,13 @@ def test_fused_lists_match_oracle_at_reference_positions(lanes):
 # ----------------------------------------------------------------------------- Langevin
 
 
-def test_langevin_matches_oracle():
+@pytest.mark.parametrize("unfused", [False, True])
+def test_langevin_matches_oracle(unfused, monkeypatch):
     # BAOAB steps with the per-atom Philox normals: same counters on both sides, so the trajectories
-    # agree to float64 rounding; two calls continue the counter, eager and graph runs are identical
+    # agree to float64 rounding; two calls continue the counter, eager and graph runs are identical.
+    # Both step loops: the fused step kernel and the per-atom kernels around the force kernel (the
+    # loop of systems too large for LDS).
+    monkeypatch.setenv("TS_NVE_UNFUSED", "1" if unfused else "0")
     from oracle import langevin as olang
     api = _api()
     w = argon_batch(2, seed=17, reps=(3, 3, 3))
@@ -411,3 +415,42 @@ def test_langevin_matches_oracle():
         assert np.abs(runs[-1][0] - ref["pos"]).max() <= 1e-9
         assert np.abs(runs[-1][1] - ref["vel"]).max() <= 1e-9 * np.abs(ref["vel"]).max()
     assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("reps", [(3, 3, 3), (9, 8, 8)])
+def test_langevin_calls_compose_and_reduce_to_nve(reps):
+    # properties that hold at any size; 9 x 8 x 8 cells (2304 atoms) exceed the LDS limit of the fused
+    # step and run the per-atom loop.  One call of K steps equals K calls of one step bitwise (the
+    # counter continues), and without friction the steps are velocity-Verlet ones up to rounding.
+    api = _api()
+    w = argon_batch(1, seed=23, reps=reps)
+    pot = w.potential
+    kTd = torch.tensor([0.03], dtype=torch.float64, device="cuda")
+    K = 6
+
+    def setup():
+        b = _batch(w)
+        nl = api.build_neighbor_list(b, pot.cutoff, w.skin)
+        pp = api.pair_params_from_spec(pot, "f64")
+        F, _, _ = api.compute_forces(b, nl, pp, "f64")
+        return b, nl, pp, F
+
+    def langevin(calls, gamma):
+        b, nl, pp, F = setup()
+        ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for k in calls:
+            api.ts_langevin_step(b, nl, pp, w.dt, w.accel, gamma, kTd, 99, ctr, k, F)
+        torch.cuda.synchronize()
+        assert int(ctr.item()) == sum(calls)
+        return b.positions(), b.velocities()
+
+    one, many = langevin([K], 0.02), langevin([1] * K, 0.02)
+    assert np.array_equal(one[0], many[0]) and np.array_equal(one[1], many[1])
+    still = langevin([K], 0.0)
+    b, nl, pp, F = setup()
+    api.ts_nve_step(b, nl, pp, w.dt, w.accel, K, F)
+    torch.cuda.synchronize()
+    L = abs(np.linalg.det(w.cell[0])) ** (1 / 3)
+    assert np.abs(still[0] - b.positions()).max() <= 1e-12 * L
+    assert np.abs(still[1] - b.velocities()).max() <= 1e-12 * np.abs(b.velocities()).max()
+    assert np.abs(one[0] - b.positions()).max() > 1e-6  # the friction and noise did act

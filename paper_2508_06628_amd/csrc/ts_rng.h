@@ -35,11 +35,22 @@ __device__ inline void atom_normals(uint64_t i, uint64_t t, uint32_t key0, uint3
   double u[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) u[k] = ((double)c[k] + 0.5) * 0x1p-32;
+  // cos(2 pi u) = cospi(2u): 2u = (2x + 1) 2^-32 is exact and the reduction of cospi is exact
   const double r0 = sqrt(-2.0 * log(u[0])), r2 = sqrt(-2.0 * log(u[2]));
-  const double t1 = 2.0 * M_PI * u[1], t3 = 2.0 * M_PI * u[3];
-  z[0] = r0 * cos(t1);
-  z[1] = r0 * sin(t1);
-  z[2] = r2 * cos(t3);
+  z[0] = r0 * cospi(2.0 * u[1]);
+  z[1] = r0 * sinpi(2.0 * u[1]);
+  z[2] = r2 * cospi(2.0 * u[3]);
+}
+
+// Component c (0, 1 or 2) of atom_normals(i, t, key0, key1) up to rounding: one logarithm and one
+// cospi, so that three lanes can share the work of one atom.
+__device__ inline double atom_normal(uint64_t i, uint64_t t, uint32_t key0, uint32_t key1, int c) {
+  uint32_t x[4] = {(uint32_t)i, (uint32_t)t, (uint32_t)(t >> 32), 0u};
+  philox4x32_10(x, key0, key1);
+  const uint32_t xa = c < 2 ? x[0] : x[2], xb = c < 2 ? x[1] : x[3];
+  const double ua = ((double)xa + 0.5) * 0x1p-32, ub = ((double)xb + 0.5) * 0x1p-32;
+  // sinpi(y) = cospi(y - 1/2), and y - 1/2 = (2 xb + 1 - 2^31) 2^-32 is exact: one cospi per lane
+  return sqrt(-2.0 * log(ua)) * cospi(2.0 * ub - (c == 1 ? 0.5 : 0.0));
 }
 
 // Parameters of the O step v = c1 v + c2 sqrt(kT_s a / m) xi, with c1 = exp(-gamma dt) and

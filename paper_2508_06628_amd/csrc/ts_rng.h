@@ -42,17 +42,6 @@ __device__ inline void atom_normals(uint64_t i, uint64_t t, uint32_t key0, uint3
   z[2] = r2 * cospi(2.0 * u[3]);
 }
 
-// Component c (0, 1 or 2) of atom_normals(i, t, key0, key1) up to rounding: one logarithm and one
-// cospi, so that three lanes can share the work of one atom.
-__device__ inline double atom_normal(uint64_t i, uint64_t t, uint32_t key0, uint32_t key1, int c) {
-  uint32_t x[4] = {(uint32_t)i, (uint32_t)t, (uint32_t)(t >> 32), 0u};
-  philox4x32_10(x, key0, key1);
-  const uint32_t xa = c < 2 ? x[0] : x[2], xb = c < 2 ? x[1] : x[3];
-  const double ua = ((double)xa + 0.5) * 0x1p-32, ub = ((double)xb + 0.5) * 0x1p-32;
-  // sinpi(y) = cospi(y - 1/2), and y - 1/2 = (2 xb + 1 - 2^31) 2^-32 is exact: one cospi per lane
-  return sqrt(-2.0 * log(ua)) * cospi(2.0 * ub - (c == 1 ? 0.5 : 0.0));
-}
-
 // Parameters of the O step v = c1 v + c2 sqrt(kT_s a / m) xi, with c1 = exp(-gamma dt) and
 // c2 = sqrt(1 - c1^2); the normals of step k of a call use the counter *rng_step + k, and the last
 // launch of the call advances *rng_step by the call's step count.

@@ -148,6 +148,24 @@ size_t ts_neighbor_workspace_bytes(int64_t n_atoms, int64_t n_systems);
    workspace too small), TS_E_CAPACITY (a system above TS_MAX_SYSTEM_ATOMS). */
 int ts_neighbor_build(const ts_batch *batch, ts_neighbor_list *nl, int32_t force, ts_stream_t stream);
 
+/* The list exported as the graph a learned potential consumes (the graph construction whose cost
+   dominates the differences between models, Section 4): every (i, j, S) of the list with
+   |d| < r_graph, d = r_j - r_i + S cell (float64 test), as one edge, in the order (system,
+   i, j, S0, S1, S2).  A full list gives both directions of every pair, a half list each pair once.
+   Outputs (device, overwritten; E = edge_offsets[S] after the call):
+     row_ptr      int64 [N + 1]  edges of atom i are row_ptr[i] .. row_ptr[i + 1] - 1
+     edge_offsets int64 [S + 1]  edges of system s are edge_offsets[s] .. edge_offsets[s + 1] - 1
+     edge_index   int64 [2][capacity]  row 0 = i (center), row 1 = j (global atom indices)
+     edge_shift   int32 [capacity][3]  integer image S, or NULL to skip
+     edge_vec     float64 [capacity][3]  d, or NULL to skip
+   Edges at positions >= capacity are not written; the counts and offsets are complete, so a caller
+   compares edge_offsets[S] with capacity after the call.  The list must be valid for the batch's
+   positions (build or update it first) and r_graph <= cutoff + skin.  Asynchronous on `stream`.
+   Errors: TS_E_INVALID (null pointers, r_graph outside (0, cutoff + skin], capacity < 0). */
+int ts_graph_export(const ts_batch *batch, const ts_neighbor_list *nl, double r_graph, int64_t *row_ptr,
+                    int64_t *edge_offsets, int64_t *edge_index, int32_t *edge_shift, double *edge_vec,
+                    int64_t capacity, ts_stream_t stream);
+
 /* Energy per system, force per atom and virial per system from the pair potential:
      E_s = 1/2 sum_{(i,j,S)} [phi(r) - shift],  F_i = sum_{(j,S)} (phi'(r)/r) d,
      W_s = -1/2 sum_{(i,j,S)} (phi'(r)/r) d (x) d  (stress = -W/V).

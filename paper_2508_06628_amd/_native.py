@@ -117,6 +117,8 @@ class TsFireState(ctypes.Structure):
 SIGNATURES = {
     "ts_neighbor_workspace_bytes": (c_size_t, [c_int64, c_int64]),
     "ts_neighbor_build": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), c_int32, c_void_p]),
+    "ts_graph_export": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), c_double, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, ctypes.c_int64, c_void_p]),
     "ts_pair_forces": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_void_p,
                                  c_void_p, c_void_p, c_void_p]),
     "ts_nve_step": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double, c_double,

@@ -250,6 +250,31 @@ def ts_neighbor_build(batch: Batch, nl: NeighborList, force: bool = True, stream
                                                                   _stream(stream)))
 
 
+def ts_graph_export(batch, nl, r_graph, row_ptr, edge_offsets, edge_index, edge_shift=None, edge_vec=None,
+                    stream=None):
+    """Edges of the list within r_graph; capacity = edge_index.shape[1]."""
+    cap = 0 if edge_index is None else int(edge_index.shape[1])
+    return N.check("ts_graph_export", N.lib().ts_graph_export(
+        ctypes.byref(batch.struct()), ctypes.byref(nl.struct()), float(r_graph), _p(row_ptr), _p(edge_offsets),
+        _p(edge_index), _p(edge_shift), _p(edge_vec), cap, _stream(stream)))
+
+
+def mlip_graph(batch, nl, r_graph, with_vec=True):
+    """Allocate and export the batch graph: dict(row_ptr, edge_offsets, edge_index [2, E], shift [E, 3],
+    vec [E, 3]).  Capacity is the list's entry count, so every edge fits (one host synchronisation)."""
+    dev = batch.pos.device
+    cap = int(nl.n_nbr.sum().item()) if batch.n_atoms else 0
+    row_ptr = torch.empty(batch.n_atoms + 1, dtype=torch.int64, device=dev)
+    offs = torch.empty(batch.n_systems + 1, dtype=torch.int64, device=dev)
+    ei = torch.empty((2, cap), dtype=torch.int64, device=dev)
+    sh = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+    vec = torch.empty((cap, 3), dtype=torch.float64, device=dev) if with_vec else None
+    ts_graph_export(batch, nl, r_graph, row_ptr, offs, ei, sh, vec)
+    e = int(offs[-1].item())
+    return dict(row_ptr=row_ptr, edge_offsets=offs, edge_index=ei[:, :e], shift=sh[:e],
+                vec=None if vec is None else vec[:e])
+
+
 def ts_pair_forces(batch, nl, pp, force, energy=None, virial=None, stream=None):
     return N.check("ts_pair_forces", N.lib().ts_pair_forces(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
                                                             ctypes.byref(pp), _p(force), _p(energy), _p(virial),

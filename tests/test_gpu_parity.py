@@ -454,3 +454,80 @@ def test_langevin_calls_compose_and_reduce_to_nve(reps):
     assert np.abs(still[0] - b.positions()).max() <= 1e-12 * L
     assert np.abs(still[1] - b.velocities()).max() <= 1e-12 * np.abs(b.velocities()).max()
     assert np.abs(one[0] - b.positions()).max() > 1e-6  # the friction and noise did act
+
+
+# ----------------------------------------------------------------------------- graph export
+
+
+def _export(api, b, nl, r, cap=None, vec=True):
+    n_e = int(nl.n_nbr.sum().item()) if cap is None else cap
+    row_ptr = torch.full((b.n_atoms + 1,), -7, dtype=torch.int64, device="cuda")
+    offs = torch.full((b.n_systems + 1,), -7, dtype=torch.int64, device="cuda")
+    ei = torch.full((2, n_e), -7, dtype=torch.int64, device="cuda")
+    sh = torch.full((n_e, 3), -99, dtype=torch.int32, device="cuda")
+    vv = torch.full((n_e, 3), np.nan, dtype=torch.float64, device="cuda") if vec else None
+    api.ts_graph_export(b, nl, r, row_ptr, offs, ei, sh, vv)
+    torch.cuda.synchronize()
+    return (row_ptr.cpu().numpy(), offs.cpu().numpy(), ei.cpu().numpy(), sh.cpu().numpy(),
+            None if vv is None else vv.cpu().numpy())
+
+
+@pytest.mark.parametrize("seed,half,r", [(40, False, 2.5), (41, False, 1.7), (42, True, 2.5)])
+def test_graph_export_matches_oracle(seed, half, r):
+    # every edge, its order, shifts and vectors, the CSR row pointer and the system offsets
+    from oracle import graph as ograph
+    from oracle.pairs import half_mask
+    api = _api()
+    w = random_small_batch(seed, n_systems=12, n_range=(1, 70), density=0.9, unwrap_spread=2)
+    b = _batch(w)
+    nl = api.build_neighbor_list(b, 2.5, 0.3, half=half)
+    ref = ograph.mlip_graph(w.pos, w.cell, w.sys_offsets, r)
+    if half:  # the half list keeps each pair once
+        keep = half_mask(ref["edge_index"][0], ref["edge_index"][1], ref["shift"])
+        sys_of = np.repeat(np.arange(w.n_systems), np.diff(w.sys_offsets))
+        for k in ("shift", "vec"):
+            ref[k] = ref[k][keep]
+        ref["edge_index"] = ref["edge_index"][:, keep]
+        ref["row_ptr"] = np.concatenate([[0], np.cumsum(np.bincount(ref["edge_index"][0], minlength=w.n_atoms))])
+        ref["edge_offsets"] = np.concatenate([[0], np.cumsum(np.bincount(sys_of[ref["edge_index"][0]],
+                                                                         minlength=w.n_systems))])
+    # no pair within 1e-9 of r_graph, where the two float64 evaluations of |d| could disagree
+    assert np.abs(np.linalg.norm(ref["vec"], axis=1) - r).min() > 1e-9
+    row_ptr, offs, ei, sh, vv = _export(api, b, nl, r)
+    E = int(offs[-1])
+    assert E == ref["edge_index"].shape[1] > 0
+    assert np.array_equal(row_ptr, ref["row_ptr"]) and np.array_equal(offs, ref["edge_offsets"])
+    assert np.array_equal(ei[:, :E], ref["edge_index"])
+    assert np.array_equal(sh[:E], ref["shift"])
+    assert np.abs(vv[:E] - ref["vec"]).max() <= 1e-12 * max(1.0, np.abs(ref["vec"]).max())
+    # a capacity below E: counts and offsets complete, the first `cap` edges written, nothing beyond
+    cap = E // 3
+    row_ptr2, offs2, ei2, sh2, _ = _export(api, b, nl, r, cap=cap, vec=False)
+    assert np.array_equal(row_ptr2, row_ptr) and np.array_equal(offs2, offs)
+    assert np.array_equal(ei2, ref["edge_index"][:, :cap]) and np.array_equal(sh2, ref["shift"][:cap])
+
+
+def test_graph_export_large_system_sampled():
+    # 2304 atoms (the sorted-bin list builder of large systems): the edges of sampled atoms against
+    # the oracle's pairs of those rows, and the pair symmetry over the whole graph
+    from oracle.pairs import system_pairs
+    api = _api()
+    w = argon_batch(1, seed=29, reps=(9, 8, 8))
+    b = _batch(w)
+    nl = api.build_neighbor_list(b, w.potential.cutoff, w.skin)
+    r = w.potential.cutoff
+    row_ptr, offs, ei, sh, vv = _export(api, b, nl, r)
+    E = int(offs[-1])
+    assert row_ptr[-1] == E and offs[0] == 0 and np.all(np.diff(row_ptr) >= 0)
+    rows = np.random.default_rng(3).choice(w.n_atoms, 24, replace=False)
+    p = system_pairs(w.pos, w.cell[0], r, rows=rows)
+    for i in rows:
+        m = p["i"] == i
+        order = np.lexsort((p["S"][m, 2], p["S"][m, 1], p["S"][m, 0], p["j"][m]))
+        lo, hi = row_ptr[i], row_ptr[i + 1]
+        assert np.all(ei[0, lo:hi] == i)
+        assert np.array_equal(ei[1, lo:hi], p["j"][m][order])
+        assert np.array_equal(sh[lo:hi], p["S"][m][order])
+        assert np.abs(vv[lo:hi] - p["d"][m][order]).max() <= 1e-11
+    keys = set(zip(ei[0, :E].tolist(), ei[1, :E].tolist(), map(tuple, sh[:E].tolist())))
+    assert all((j, i, (-a, -b_, -c)) in keys for i, j, (a, b_, c) in keys)

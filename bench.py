@@ -107,6 +107,35 @@ def langevin_throughput(api, torch, w, steps, chunk, bin_factor, gamma=0.01, tem
                 us_per_step=round(ms * 1e3 / n, 2), gamma_per_fs=gamma, temperature_K=temp_k, rebuilds=int(st[2]))
 
 
+def graph_export(api, torch, w, bin_factor, reps=50):
+    """Export of the batch graph at r_graph = r_c from a valid list: mean time per export (HIP events
+    on the launch stream) and its algorithmic bytes (list entries read once, positions, edges written
+    with index pairs, integer shifts and vectors, the row pointer)."""
+    pot = w.potential
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=bin_factor, margin=1.3)
+    entries = int(nl.n_nbr.sum().item())
+    g = api.mlip_graph(b, nl, pot.cutoff)
+    E = int(g["edge_offsets"][-1].item())
+    row_ptr, offs = torch.empty_like(g["row_ptr"]), torch.empty_like(g["edge_offsets"])
+    ei = torch.empty((2, E), dtype=torch.int64, device="cuda")
+    sh = torch.empty((E, 3), dtype=torch.int32, device="cuda")
+    vec = torch.empty((E, 3), dtype=torch.float64, device="cuda")
+    api.ts_graph_export(b, nl, pot.cutoff, row_ptr, offs, ei, sh, vec)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        api.ts_graph_export(b, nl, pot.cutoff, row_ptr, offs, ei, sh, vec)
+    ev1.record()
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / reps
+    alg = 4 * entries + 4 * w.n_atoms + 24 * w.n_atoms + 8 * (w.n_atoms + 1) + (16 + 12 + 24) * E
+    return dict(us_per_export=round(us, 2), edges=E, list_entries=entries, edges_per_s=round(E / (us * 1e-6), 1),
+                alg_bytes=alg, achieved_GBps=round(alg / (us * 1e-6) / 1e9, 1),
+                frac_hbm=round(alg / (us * 1e-6) / 8e12, 4))
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary (FETCH_SIZE +
     WRITE_SIZE, scaled by a device copy of known size), or None once the kernel sources have
@@ -344,6 +373,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-langevin", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-export measurement")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fire", action="store_true", help="skip the copper FIRE and soft-sphere workloads")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -399,6 +429,9 @@ def main():
     if not args.no_langevin:
         out["langevin"] = langevin_throughput(api, torch, w, args.steps, args.chunk, args.bin_factor)
         log(f"langevin: {out['langevin']}")
+    if not args.no_graph:
+        out["graph_export"] = graph_export(api, torch, w, args.bin_factor)
+        log(f"graph export: {out['graph_export']}")
     if not args.no_adjoint:
         a = adjoint_throughput(api, torch, 16, args.adjoint_steps, 50)
         out["adjoint"] = a

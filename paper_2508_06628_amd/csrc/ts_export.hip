@@ -4,9 +4,10 @@
 // paper attributes most of the speed differences between learned potentials to this graph
 // construction (Section 4).
 //
-// Four launches: per-atom edge counts (one lane per atom over its list row), a scan of the counts
-// inside each system (one workgroup per system), a scan of the system totals (one workgroup), and
-// the edge writes (one lane per atom; the row order is already the (j, S) order).
+// Four launches: per-atom edge counts (eight lanes per atom row), a scan of the counts inside each
+// system (one workgroup per system), a scan of the system totals (one workgroup), and the edge
+// writes (one wavefront per atom row, consecutive lanes writing consecutive edges; the row order
+// is already the (j, S) order).
 #include "ts_internal.h"
 
 namespace ts {
@@ -37,21 +38,29 @@ __device__ inline void edge_vector(const ExportArgs &a, int64_t i, int64_t j, ui
     d[c] = fma(s2, h[6 + c], fma(s1, h[3 + c], fma(s0, h[c], a.pos[c * a.st + j] - a.pos[c * a.st + i])));
 }
 
+// Edge counts: kRowBlock lanes per atom, one row block (kRowBlock contiguous entries) per step, so
+// that a wavefront load covers the same block of eight consecutive atoms: 256 contiguous bytes.
 __global__ void __launch_bounds__(kExportThreads) k_edge_count(ExportArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int s = a.sys_idx[i];
-  const int64_t a0 = a.offs[s];
-  const double *h = a.cell + 9 * (int64_t)s;
-  const int nn = a.n_nbr[i];
-  int64_t c = 0;
-  for (int k = 0; k < nn; ++k) {
-    const uint32_t e = a.nbr[row_index(k, i, a.st)];
-    double d[3];
-    edge_vector(a, i, a0 + entry_j(e), e, h, d);
-    c += (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < a.r2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / kRowBlock;
+  const int sub = (int)(t % kRowBlock);
+  const bool own = i < a.n;
+  int c = 0;
+  if (own) {
+    const int s = a.sys_idx[i];
+    const int64_t a0 = a.offs[s];
+    const double *h = a.cell + 9 * (int64_t)s;
+    const int nn = a.n_nbr[i];
+    for (int k = sub; k < nn; k += kRowBlock) {
+      const uint32_t e = a.nbr[row_index(k, i, a.st)];
+      double d[3];
+      edge_vector(a, i, a0 + entry_j(e), e, h, d);
+      c += (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < a.r2;
+    }
   }
-  a.row_ptr[i] = c;
+#pragma unroll
+  for (int o = 1; o < kRowBlock; o <<= 1) c += __shfl_xor(c, o, kRowBlock);
+  if (own && sub == 0) a.row_ptr[i] = c;
 }
 
 // Exclusive scan of v over the workgroup; *total receives the sum.
@@ -111,36 +120,48 @@ __global__ void __launch_bounds__(kExportThreads) k_edge_scan_total(ExportArgs a
   }
 }
 
+// One wavefront per atom: its 64 lanes test 64 row entries at a time (the row is in (j, S) order,
+// so a ballot and a population count give each edge its position).
+__device__ inline int64_t wave_atom() { return ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; }
+
 __global__ void __launch_bounds__(kExportThreads) k_edge_write(ExportArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+  const int64_t i = wave_atom();
+  if (i >= a.n) return;  // uniform over the wavefront
+  const int lane = threadIdx.x % kWave;
+  const uint64_t below = (1ull << lane) - 1ull;
   const int s = a.sys_idx[i];
   const int64_t a0 = a.offs[s];
   const double *h = a.cell + 9 * (int64_t)s;
   int64_t p = a.edge_offsets[s] + a.row_ptr[i];
-  a.row_ptr[i] = p;
+  if (lane == 0) a.row_ptr[i] = p;
   const int nn = a.n_nbr[i];
-  for (int k = 0; k < nn; ++k) {
-    const uint32_t e = a.nbr[row_index(k, i, a.st)];
-    const int64_t j = a0 + entry_j(e);
-    double d[3];
-    edge_vector(a, i, j, e, h, d);
-    if (!((d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < a.r2)) continue;
-    if (p < a.capacity) {
-      a.edge_index[p] = i;
-      a.edge_index[a.capacity + p] = j;
+  for (int k0 = 0; k0 < nn; k0 += kWave) {
+    const int k = k0 + lane;
+    bool in = false;
+    uint32_t e = 0;
+    double d[3] = {0.0, 0.0, 0.0};
+    if (k < nn) {
+      e = a.nbr[row_index(k, i, a.st)];
+      edge_vector(a, i, a0 + entry_j(e), e, h, d);
+      in = (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < a.r2;
+    }
+    const uint64_t mask = __ballot(in);
+    const int64_t q = p + __popcll(mask & below);
+    if (in && q < a.capacity) {
+      a.edge_index[q] = i;
+      a.edge_index[a.capacity + q] = a0 + entry_j(e);
       if (a.edge_shift) {
-        a.edge_shift[3 * p] = entry_s0(e);
-        a.edge_shift[3 * p + 1] = entry_s1(e);
-        a.edge_shift[3 * p + 2] = entry_s2(e);
+        a.edge_shift[3 * q] = entry_s0(e);
+        a.edge_shift[3 * q + 1] = entry_s1(e);
+        a.edge_shift[3 * q + 2] = entry_s2(e);
       }
       if (a.edge_vec) {
-        a.edge_vec[3 * p] = d[0];
-        a.edge_vec[3 * p + 1] = d[1];
-        a.edge_vec[3 * p + 2] = d[2];
+        a.edge_vec[3 * q] = d[0];
+        a.edge_vec[3 * q + 1] = d[1];
+        a.edge_vec[3 * q + 2] = d[2];
       }
     }
-    ++p;
+    p += __popcll(mask);
   }
 }
 
@@ -175,9 +196,12 @@ extern "C" int ts_graph_export(const ts_batch *batch, const ts_neighbor_list *nl
   a.capacity = capacity;
   a.n_sys = (int)batch->n_systems;
   hipStream_t st = ts::as_stream(stream);
-  const dim3 g((unsigned)ts::ceil_div(a.n > 0 ? a.n : 1, ts::kExportThreads)), b(ts::kExportThreads);
+  const int64_t waves_per_block = ts::kExportThreads / ts::kWave;
+  if (ts::ceil_div(a.n, waves_per_block) > 0x7fffffff) return TS_E_CAPACITY;
+  const dim3 g((unsigned)ts::ceil_div(a.n > 0 ? a.n : 1, waves_per_block)), b(ts::kExportThreads);
   if (a.n > 0) {
-    hipLaunchKernelGGL(ts::k_edge_count, g, b, 0, st, a);
+    const dim3 gc((unsigned)ts::ceil_div(a.n * ts::kRowBlock, ts::kExportThreads));
+    hipLaunchKernelGGL(ts::k_edge_count, gc, b, 0, st, a);
     TS_LAUNCH_CHECK();
   }
   if (a.n_sys > 0) {

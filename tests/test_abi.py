@@ -136,3 +136,22 @@ def test_host_argument_checks():
     big, hbig = _fake_batch(N, [0, N.TS_MAX_SYSTEM_ATOMS + 1])
     assert L.ts_neighbor_build(by(big), by(_nl(N, N.TS_MAX_SYSTEM_ATOMS + 1, 1)), 1, None) == N.TS_E_CAPACITY
     assert L.ts_strerror(N.TS_E_CAPACITY).decode() == "size exceeds a library limit"
+    # Langevin: negative or non-finite friction, missing temperature or counter, negative step count
+    kT, ctr = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    pp = by(_pp(N))
+    assert L.ts_langevin_step(by(b), by(ok_nl), pp, 1.0, 1.0, -0.1, kT, 1, ctr, 5, F, 0, None) == N.TS_E_INVALID
+    assert L.ts_langevin_step(by(b), by(ok_nl), pp, 1.0, 1.0, float("nan"), kT, 1, ctr, 5, F, 0,
+                              None) == N.TS_E_INVALID
+    assert L.ts_langevin_step(by(b), by(ok_nl), pp, 1.0, 1.0, 0.1, None, 1, ctr, 5, F, 0, None) == N.TS_E_INVALID
+    assert L.ts_langevin_step(by(b), by(ok_nl), pp, 1.0, 1.0, 0.1, kT, 1, None, 5, F, 0, None) == N.TS_E_INVALID
+    assert L.ts_langevin_step(by(b), by(ok_nl), pp, 1.0, 1.0, 0.1, kT, 1, ctr, -1, F, 0, None) == N.TS_E_INVALID
+    assert L.ts_langevin_step(by(nv), by(ok_nl), pp, 1.0, 1.0, 0.1, kT, 1, ctr, 5, F, 0, None) == N.TS_E_INVALID
+    # graph export: radius beyond the list radius or not positive, missing outputs, negative capacity
+    rp, eo, ei = ctypes.c_void_p(0x4000), ctypes.c_void_p(0x5000), ctypes.c_void_p(0x6000)
+    r_list = ok_nl.cutoff + ok_nl.skin
+    assert L.ts_graph_export(by(b), by(ok_nl), r_list * 1.01, rp, eo, ei, None, None, 10, None) == N.TS_E_INVALID
+    assert L.ts_graph_export(by(b), by(ok_nl), 0.0, rp, eo, ei, None, None, 10, None) == N.TS_E_INVALID
+    assert L.ts_graph_export(by(b), by(ok_nl), 1.0, None, eo, ei, None, None, 10, None) == N.TS_E_INVALID
+    assert L.ts_graph_export(by(b), by(ok_nl), 1.0, rp, None, ei, None, None, 10, None) == N.TS_E_INVALID
+    assert L.ts_graph_export(by(b), by(ok_nl), 1.0, rp, eo, None, None, None, 10, None) == N.TS_E_INVALID
+    assert L.ts_graph_export(by(b), by(ok_nl), 1.0, rp, eo, ei, None, None, -1, None) == N.TS_E_INVALID

@@ -531,3 +531,27 @@ def test_graph_export_large_system_sampled():
         assert np.abs(vv[lo:hi] - p["d"][m][order]).max() <= 1e-11
     keys = set(zip(ei[0, :E].tolist(), ei[1, :E].tolist(), map(tuple, sh[:E].tolist())))
     assert all((j, i, (-a, -b_, -c)) in keys for i, j, (a, b_, c) in keys)
+
+
+@pytest.mark.parametrize("unfused", [False, True])
+def test_langevin_fp32_forces_short_run(unfused, monkeypatch):
+    # the precision of the benchmark: float32 pair function, float64 integration.  Over three steps
+    # the float32 force error (1e-5 relative) moves positions by well under 1e-8 A.
+    monkeypatch.setenv("TS_NVE_UNFUSED", "1" if unfused else "0")
+    from oracle import langevin as olang
+    api = _api()
+    w = argon_batch(3, seed=31, reps=(3, 3, 3))
+    pot = w.potential
+    kT = np.array([0.01, 0.02, 0.03])
+    gamma, seed, K = 0.02, 2 ** 40 + 7, 3
+    ref = olang.baoab(w.pos, w.vel, w.mass, w.cell, w.sys_offsets, w.species, pot, w.dt, K, w.accel, gamma, kT, seed)
+    b = _batch(w)
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin)
+    pp = api.pair_params_from_spec(pot, "f32")
+    F, _, _ = api.compute_forces(b, nl, pp, "f32")
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    api.ts_langevin_step(b, nl, pp, w.dt, w.accel, gamma, torch.tensor(kT, device="cuda"), seed, ctr, K, F)
+    torch.cuda.synchronize()
+    assert int(ctr.item()) == K
+    assert np.abs(b.positions() - ref["pos"]).max() <= 1e-8
+    assert np.abs(b.velocities() - ref["vel"]).max() <= 1e-7 * np.abs(ref["vel"]).max()

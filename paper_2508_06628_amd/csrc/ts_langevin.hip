@@ -98,6 +98,7 @@ extern "C" int ts_langevin_step(const ts_batch *batch, ts_neighbor_list *nl, con
   TS_CHECK_ARG(force != nullptr && kT != nullptr && rng_step != nullptr);
   TS_CHECK_ARG(std::isfinite(dt) && dt > 0.0 && std::isfinite(accel) && accel > 0.0 && n_steps >= 0);
   TS_CHECK_ARG(std::isfinite(gamma) && gamma >= 0.0 && batch->n_atoms < ((int64_t)1 << 32));
+  if (n_steps == 0) return TS_OK;  // nothing to advance, the counter included
   std::string key("langevin");
   ts::key_add(key, *batch);
   ts::key_add(key, *nl);

@@ -444,6 +444,8 @@ def test_langevin_calls_compose_and_reduce_to_nve(reps):
         assert int(ctr.item()) == sum(calls)
         return b.positions(), b.velocities()
 
+    zero = langevin([0], 0.02)  # a call of no steps changes nothing, the counter included
+    assert np.array_equal(zero[0], w.pos) and np.array_equal(zero[1], w.vel)
     one, many = langevin([K], 0.02), langevin([1] * K, 0.02)
     assert np.array_equal(one[0], many[0]) and np.array_equal(one[1], many[1])
     still = langevin([K], 0.0)
@@ -500,6 +502,11 @@ def test_graph_export_matches_oracle(seed, half, r):
     assert np.array_equal(ei[:, :E], ref["edge_index"])
     assert np.array_equal(sh[:E], ref["shift"])
     assert np.abs(vv[:E] - ref["vec"]).max() <= 1e-12 * max(1.0, np.abs(ref["vec"]).max())
+    # capacity 0 and no edge buffers: the counts and offsets only
+    rp0 = torch.empty(b.n_atoms + 1, dtype=torch.int64, device="cuda")
+    of0 = torch.empty(b.n_systems + 1, dtype=torch.int64, device="cuda")
+    api.ts_graph_export(b, nl, r, rp0, of0, None)
+    assert np.array_equal(rp0.cpu().numpy(), row_ptr) and np.array_equal(of0.cpu().numpy(), offs)
     # a capacity below E: counts and offsets complete, the first `cap` edges written, nothing beyond
     cap = E // 3
     row_ptr2, offs2, ei2, sh2, _ = _export(api, b, nl, r, cap=cap, vec=False)

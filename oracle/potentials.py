@@ -93,3 +93,18 @@ def dg_dparams(kind: str, p: np.ndarray, r: np.ndarray) -> np.ndarray:
     else:
         raise ValueError(kind)
     return out
+
+
+def lorentz_berthelot(eps, sigma) -> np.ndarray:
+    """LJ parameter table of a mixture from per-species (epsilon, sigma) by the Lorentz-Berthelot
+    rules: epsilon_ab = sqrt(epsilon_a epsilon_b) (geometric mean), sigma_ab = (sigma_a + sigma_b) / 2
+    (arithmetic mean).  Returns (S, S, 3) rows (epsilon_ab, sigma_ab, 0)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    n = eps.shape[0]
+    out = np.zeros((n, n, 3))
+    for a in range(n):
+        for b in range(n):
+            out[a, b, 0] = np.sqrt(eps[a] * eps[b])
+            out[a, b, 1] = 0.5 * (sigma[a] + sigma[b])
+    return out

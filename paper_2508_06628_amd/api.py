@@ -108,6 +108,20 @@ def pair_params(kind: str, params, cutoff: float, shift_energy: bool = False, pr
     return pp
 
 
+def lorentz_berthelot(eps, sigma) -> np.ndarray:
+    """(S, S, 3) LJ table of a mixture: epsilon_ab = sqrt(epsilon_a epsilon_b),
+    sigma_ab = (sigma_a + sigma_b) / 2 (the Lorentz-Berthelot rules); pass it as ``params``."""
+    e = np.asarray(eps, dtype=np.float64).reshape(-1)
+    s = np.asarray(sigma, dtype=np.float64).reshape(-1)
+    if e.shape != s.shape or e.size < 1 or e.size > N.TS_MAX_SPECIES or np.any(e < 0) or np.any(s <= 0):
+        raise ValueError("lorentz_berthelot: one non-negative epsilon and one positive sigma per species, "
+                         f"at most {N.TS_MAX_SPECIES} species")
+    table = np.zeros((e.size, e.size, 3))
+    table[:, :, 0] = np.sqrt(np.outer(e, e))
+    table[:, :, 1] = 0.5 * (s[:, None] + s[None, :])
+    return table
+
+
 def pair_params_from_spec(spec, prec: str = "f32") -> N.TsPairParams:
     return pair_params(spec.kind, spec.params, spec.cutoff, spec.shift_energy, prec)
 

@@ -562,3 +562,24 @@ def test_langevin_fp32_forces_short_run(unfused, monkeypatch):
     assert int(ctr.item()) == K
     assert np.abs(b.positions() - ref["pos"]).max() <= 1e-8
     assert np.abs(b.velocities() - ref["vel"]).max() <= 1e-7 * np.abs(ref["vel"]).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lorentz_berthelot_mixture_forces(prec):
+    # a three-species LJ mixture whose table comes from the mixing rules: the package's table on the
+    # GPU, the oracle's own table on the CPU
+    from oracle.potentials import lorentz_berthelot
+    from workloads import PotentialSpec
+    api = _api()
+    eps, sig = [1.0, 0.6, 1.4], [1.0, 1.15, 0.9]
+    w = random_small_batch(77, n_systems=6, n_range=(10, 90), kind="lj", n_species=3, unwrap_spread=1)
+    gpu_pot = PotentialSpec("lj", api.lorentz_berthelot(eps, sig), 2.5, True)
+    ref_pot = PotentialSpec("lj", lorentz_berthelot(eps, sig), 2.5, True)
+    b = _batch(w)
+    nl = api.build_neighbor_list(b, 2.5, 0.2, bin_factor=2)
+    F, E, W = api.compute_forces(b, nl, api.pair_params_from_spec(gpu_pot, prec), prec)
+    E_ref, F_ref, W_ref = oforces.batch_efw(w.pos, w.cell, w.sys_offsets, w.species, ref_pot)
+    A, se, sw = force_scales(w.pos, w.cell, w.sys_offsets, w.species, ref_pot)
+    assert_forces_close(F.T.double().cpu().numpy(), F_ref, A, 1e-10 if prec == "f64" else 1e-5)
+    erel = 1e-10 if prec == "f64" else 1e-6
+    assert np.all(np.abs(E.cpu().numpy() - E_ref) <= erel * se + 1e-300)

@@ -313,13 +313,29 @@ def soft_sphere(api, torch, fire_iters=4000, nve_steps=2000, chunk=100):
     torch.cuda.synchronize()
     nve_ms = e0.elapsed_time(e1)
     st = nl.read_status()
+    # Langevin at the same temperature (the per-atom loop of systems above the LDS limit)
+    kT = torch.full((w.n_systems,), float(w.extra["nve_temperature"]), dtype=torch.float64, device=b.device)
+    ctr = torch.zeros(1, dtype=torch.int64, device=b.device)
+    api.ts_langevin_step(b, nl, pp, w.dt, w.accel, 1.0, kT, 11, ctr, chunk, F)  # instantiate the graph
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(nve_steps // chunk):
+        api.ts_langevin_step(b, nl, pp, w.dt, w.accel, 1.0, kT, 11, ctr, chunk, F)
+    e1.record()
+    torch.cuda.synchronize()
+    lang_ms = e0.elapsed_time(e1)
+    st_l = nl.read_status()
+    if st_l[1] or st_l[3] or st_l[4]:
+        raise RuntimeError(f"neighbor list status after the soft-sphere Langevin run: {st_l.tolist()}")
     return dict(workload="soft_sphere_binary_8x32000", n_atoms=b.n_atoms,
                 fire=dict(seconds=round(fire_ms * 1e-3, 4), iterations=int(it.max()),
                           converged=int(fs.converged.sum().item()), value=round(fire_work / (fire_ms * 1e-3), 1),
                           unit="atom-iterations/s"),
                 nve=dict(steps=nve_steps, ms_per_step=round(nve_ms / nve_steps, 5),
                          value=round(w.n_atoms * nve_steps / (nve_ms * 1e-3), 1), unit="atom-steps/s",
-                         system_rebuilds=int(st[2])))
+                         system_rebuilds=int(st[2])),
+                langevin=dict(steps=nve_steps, gamma=1.0, ms_per_step=round(lang_ms / nve_steps, 5),
+                              value=round(w.n_atoms * nve_steps / (lang_ms * 1e-3), 1), unit="atom-steps/s"))
 
 
 def cpu_baseline(w, steps=2):

@@ -215,36 +215,63 @@ def plain_path(api, torch, w, steps, bin_factor):
     return dict(value=w.n_atoms * steps / dt, steps=steps, seconds=round(dt, 4))
 
 
-def adjoint_throughput(api, torch, n_systems, n_steps, checkpoint):
+def adjoint_throughput(api, torch, n_systems, n_steps, checkpoint, plain=True):
+    """Backward pass (segment recomputation + reverse steps) of the checkpointed trajectory gradient
+    of the 16 x 864 argon batch, and the same work one system at a time without graphs (the plain
+    path)."""
     from paper_2508_06628_amd.trajectory import TrajectoryRDF
     from workloads import argon_adjoint_batch
     w = argon_adjoint_batch(n_systems, n_steps=n_steps)
-    eng = TrajectoryRDF(w, n_steps, checkpoint, prec="f32")
-    pos0 = eng.batch.pos.clone()
     eps, sig = float(w.potential.params[0, 0, 0]), float(w.potential.params[0, 0, 1])
-    g_t = eng.run(eps * 1.05, sig * 1.05, pos0).clone()
-    eng.set_target(g_t)
-    eng.forward(eps, sig, pos0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    eng.forward(eps, sig, pos0)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    de, ds, dr = eng.backward()
-    torch.cuda.synchronize()
-    t_bwd = time.perf_counter() - t0
-    return dict(value=w.n_atoms * n_steps / t_bwd, unit="atom-steps/s (backward: recompute + reverse)",
-                workload=f"argon_adjoint_{n_systems}x864_{n_steps}steps_ckpt{checkpoint}",
-                steps_per_s=round(n_steps / t_bwd, 2), backward_s=round(t_bwd, 3), forward_s=round(t_fwd, 3),
-                loss=float(eng.loss.item()), dL_deps=de, dL_dsigma=ds)
+
+    def one(ww, use_graph):
+        eng = TrajectoryRDF(ww, n_steps, checkpoint, prec="f32", use_graph=use_graph)
+        pos0 = eng.batch.pos.clone()
+        g_t = eng.run(eps * 1.05, sig * 1.05, pos0).clone()
+        eng.set_target(g_t)
+        eng.forward(eps, sig, pos0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eng.forward(eps, sig, pos0)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        de, ds, dr = eng.backward()
+        torch.cuda.synchronize()
+        t_bwd = time.perf_counter() - t0
+        eng.check_status()
+        return eng, t_fwd, t_bwd, de, ds
+
+    eng, t_fwd, t_bwd, de, ds = one(w, True)
+    out = dict(value=w.n_atoms * n_steps / t_bwd, unit="atom-steps/s (backward: recompute + reverse)",
+               workload=f"argon_adjoint_{n_systems}x864_{n_steps}steps_ckpt{checkpoint}",
+               steps_per_s=round(n_steps / t_bwd, 2), backward_s=round(t_bwd, 3), forward_s=round(t_fwd, 3),
+               loss=float(eng.loss.item()), dL_deps=de, dL_dsigma=ds)
+    if plain:
+        t_plain = 0.0
+        for s in range(n_systems):
+            _, _, tb, _, _ = one(w.subset([s]), False)
+            t_plain += tb
+        out["plain_path"] = dict(value=round(w.n_atoms * n_steps / t_plain, 1), backward_s=round(t_plain, 3),
+                                 unit="atom-steps/s (backward, one system at a time, no graphs)",
+                                 speedup_batched_vs_plain=round(t_plain / t_bwd, 2))
+    return out
+
+
+def _check_list(nl, what):
+    st = nl.read_status()
+    if st[1] or st[3] or st[4]:
+        raise RuntimeError(f"neighbor list status after {what}: {st.tolist()}")
+    return st
 
 
 def fire_copper(api, torch, max_iter=20000, skin=1.0):
-    """Batched FIRE of positions and cell on the uneven 512-system Morse copper batch, in one
-    persistent launch (its tail handed to the per-iteration kernels), until every system has
-    max |F| < fmax (and the cell force too).  The list skin is a tuning parameter of the relaxation
-    (forces do not depend on it): 1 A trades longer rows for fewer rebuilds under cell changes."""
+    """Batched FIRE of positions and cell on the uneven 512-system Morse copper batch until every
+    system has max |F| < fmax (and the cell force too): repeated ts_fire_step calls, each one
+    persistent launch (largest system first, a converged system frees its workgroup) plus a bounded
+    tail of per-iteration launches; the host reads the convergence flags between calls.  The list
+    skin is a tuning parameter of the relaxation (forces do not depend on it): 1 A trades longer
+    rows for fewer rebuilds under cell changes."""
     from workloads import copper_uneven_batch
     w = copper_uneven_batch(512, seed=2)
     pot = w.potential
@@ -258,24 +285,58 @@ def fire_copper(api, torch, max_iter=20000, skin=1.0):
     fs = api.FireState(b, cfg)
     F = api.force_buffer(b, w.pair_prec)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    api.ts_fire_step(b, fs, cfg, nl, pp, max_iter, F, persistent=True)
-    e1.record()
+    t0 = time.perf_counter()
+    calls = api.fire_relax(b, fs, cfg, nl, pp, F)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    sec = time.perf_counter() - t0
+    st = _check_list(nl, "copper FIRE")
     it = fs.n_iter.cpu().numpy()
     work = float((it * np.diff(b.h_offsets)).sum())
     return dict(workload=f"copper_morse_fire_cell_{w.n_systems}_uneven", n_atoms=b.n_atoms, skin_A=skin,
-                seconds=round(ms * 1e-3, 4),
+                seconds=round(sec, 4), calls=calls,
                 converged=int(fs.converged.sum().item()), n_systems=w.n_systems, iterations_mean=round(float(it.mean()), 1),
-                iterations_max=int(it.max()), value=round(work / (ms * 1e-3), 1), unit="atom-iterations/s",
-                list_rebuilds=int(nl.read_status()[2]))
+                iterations_max=int(it.max()), value=round(work / sec, 1), unit="atom-iterations/s",
+                list_rebuilds=int(st[2]), list_max_nbr=int(st[0]), list_capacity=nl.max_nbr)
 
 
-def soft_sphere(api, torch, fire_iters=4000, nve_steps=2000, chunk=100):
-    """Soft-sphere jamming batch (8 x 32000, binary): batched FIRE (capped at fire_iters), then NVE
-    at T = 1e-4 (reduced units) from Maxwell-Boltzmann velocities."""
+def copper_force_roofline(api, torch, reps=50):
+    """The pair-force kernel on the uneven 512-system copper batch (72 M list entries, ~290 MB of
+    list: beyond the 256 MB Infinity Cache, so its bytes come from HBM): average launch duration
+    timed with events on the launch stream, and its algorithmic bytes."""
+    from workloads import copper_uneven_batch
+    w = copper_uneven_batch(512, seed=2)
+    pot = w.potential
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=2, margin=1.2)
+    pp = api.pair_params_from_spec(pot, w.pair_prec)
+    F = api.force_buffer(b, w.pair_prec)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        api.ts_pair_forces(b, nl, pp, F, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        api.ts_pair_forces(b, nl, pp, F, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    _check_list(nl, "copper force timing")
+    avg_ms = e0.elapsed_time(e1) / reps
+    entries = int(nl.n_nbr.sum().item())
+    n = b.n_atoms
+    alg = n * (24 + 4 + 12) + 4 * entries + w.n_systems * (8 + 72)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    tl = nl.lanes_per_atom if nl.lanes_per_atom > 0 else (8 if n * 4 // 64 < 2048 else 4)
+    return dict(workload=f"copper_morse_forces_{w.n_systems}_uneven", kernel=f"ts::k_step<1, float, {tl}, 3>",
+                bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), avg_launch_us=round(avg_ms * 1e3, 2),
+                alg_bytes_per_launch=alg, list_entries=entries, mean_list_len=round(entries / n, 2), n_atoms=n)
+
+
+def soft_sphere(api, torch, fire_seconds=60.0, nve_steps=2000, chunk=100):
+    """Soft-sphere jamming batch (8 x 32000, binary): batched FIRE to max |F| < 1e-6 (capped by wall
+    time, reported), then NVE at T = 1e-4 (reduced units) from Maxwell-Boltzmann velocities, and
+    Langevin at the same temperature."""
     from workloads import maxwell_boltzmann, soft_sphere_jamming_batch
     w = soft_sphere_jamming_batch(8, 32000, seed=4)
     pot = w.potential
@@ -286,19 +347,27 @@ def soft_sphere(api, torch, fire_iters=4000, nve_steps=2000, chunk=100):
     fs = api.FireState(b, cfg)
     F = api.force_buffer(b, w.pair_prec)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    done = 0
-    while done < fire_iters:
-        api.ts_fire_step(b, fs, cfg, nl, pp, 500, F)
-        done += 500
+    t0 = time.perf_counter()
+    calls = 0
+    capped = False
+    while True:
+        api.ts_fire_step(b, fs, cfg, nl, pp, 256, F)
+        calls += 1
         if fs.converged.all().item():
             break
-    e1.record()
+        if time.perf_counter() - t0 > fire_seconds:
+            capped = True
+            break
     torch.cuda.synchronize()
-    fire_ms = e0.elapsed_time(e1)
+    fire_s = time.perf_counter() - t0
+    _check_list(nl, "soft-sphere FIRE")
     it = fs.n_iter.cpu().numpy()
     fire_work = float((it * np.diff(b.h_offsets)).sum())
+    fire = dict(seconds=round(fire_s, 3), iterations_max=int(it.max()), iterations_min=int(it.min()),
+                converged=int(fs.converged.sum().item()), n_systems=w.n_systems, fmax=float(cfg.fmax),
+                capped_at_seconds=fire_seconds if capped else None,
+                value=round(fire_work / fire_s, 1), unit="atom-iterations/s")
+    log(f"soft-sphere FIRE: {fire}")
     rng = np.random.default_rng(5)
     v = maxwell_boltzmann(rng, w.mass, w.extra["nve_temperature"], k_b=1.0, accel=1.0)
     b.vel.copy_(torch.tensor(np.ascontiguousarray(v.T), dtype=torch.float64, device=b.device))
@@ -306,13 +375,14 @@ def soft_sphere(api, torch, fire_iters=4000, nve_steps=2000, chunk=100):
     api.ts_nve_step(b, nl, pp, w.dt, w.accel, chunk, F, use_graph=True)  # instantiate the graph
     torch.cuda.synchronize()
     nl.status.zero_()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(nve_steps // chunk):
         api.ts_nve_step(b, nl, pp, w.dt, w.accel, chunk, F, use_graph=True)
     e1.record()
     torch.cuda.synchronize()
     nve_ms = e0.elapsed_time(e1)
-    st = nl.read_status()
+    st = _check_list(nl, "soft-sphere NVE")
     # Langevin at the same temperature (the per-atom loop of systems above the LDS limit)
     kT = torch.full((w.n_systems,), float(w.extra["nve_temperature"]), dtype=torch.float64, device=b.device)
     ctr = torch.zeros(1, dtype=torch.int64, device=b.device)
@@ -324,30 +394,46 @@ def soft_sphere(api, torch, fire_iters=4000, nve_steps=2000, chunk=100):
     e1.record()
     torch.cuda.synchronize()
     lang_ms = e0.elapsed_time(e1)
-    st_l = nl.read_status()
-    if st_l[1] or st_l[3] or st_l[4]:
-        raise RuntimeError(f"neighbor list status after the soft-sphere Langevin run: {st_l.tolist()}")
-    return dict(workload="soft_sphere_binary_8x32000", n_atoms=b.n_atoms,
-                fire=dict(seconds=round(fire_ms * 1e-3, 4), iterations=int(it.max()),
-                          converged=int(fs.converged.sum().item()), value=round(fire_work / (fire_ms * 1e-3), 1),
-                          unit="atom-iterations/s"),
+    _check_list(nl, "soft-sphere Langevin")
+    return dict(workload="soft_sphere_binary_8x32000", n_atoms=b.n_atoms, fire=fire,
                 nve=dict(steps=nve_steps, ms_per_step=round(nve_ms / nve_steps, 5),
                          value=round(w.n_atoms * nve_steps / (nve_ms * 1e-3), 1), unit="atom-steps/s",
-                         system_rebuilds=int(st[2])),
+                         system_rebuilds=int(st[2]), start="FIRE end state" + (" (capped)" if capped else "")),
                 langevin=dict(steps=nve_steps, gamma=1.0, ms_per_step=round(lang_ms / nve_steps, 5),
                               value=round(w.n_atoms * nve_steps / (lang_ms * 1e-3), 1), unit="atom-steps/s"))
 
 
-def cpu_baseline(w, steps=2):
-    """The FP64 oracle (brute-force pair search) on one system of the workload, on the host."""
+def _oracle_nve_task(args):
+    from threadpoolctl import threadpool_limits
     from oracle import integrate
-    ws = w.subset([0])
+    ws, steps = args
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        integrate.nve(ws.pos, ws.vel, ws.mass, ws.cell, ws.sys_offsets, ws.species, ws.potential, ws.dt, steps,
+                      ws.accel)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(w, steps=2):
+    """The FP64 oracle (brute-force pair sums) on the host cores: one system of the workload per
+    process, as many processes as cores (at most one per system), each running ``steps`` NVE steps
+    (plus the initial force evaluation); throughput = atoms x steps of all processes / wall time,
+    extrapolated to the whole batch (systems are independent)."""
+    import multiprocessing as mp
+    cores = min(os.cpu_count() or 1, w.n_systems)
+    tasks = [(w.subset([s]), steps) for s in range(cores)]
+    # fresh interpreters (the parent holds a GPU context; the children only run NumPy)
+    ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    integrate.nve(ws.pos, ws.vel, ws.mass, ws.cell, ws.sys_offsets, ws.species, ws.potential, ws.dt, steps, ws.accel)
-    dt = time.perf_counter() - t0
-    return dict(value=round(ws.n_atoms * steps / dt, 2), unit="atom-steps/s", cores=1, kind="oracle",
-                sample=f"1 system x {ws.n_atoms} atoms, {steps} NVE steps (+1 initial force evaluation), "
-                       f"{dt:.1f} s, single process float64 NumPy")
+    with ctx.Pool(cores) as pool:
+        per = pool.map(_oracle_nve_task, tasks)
+    wall = time.perf_counter() - t0
+    atoms = sum(t[0].n_atoms for t in tasks)
+    return dict(value=round(atoms * steps / wall, 2), unit="atom-steps/s", cores=cores, kind="oracle",
+                sample=f"{cores} systems x {tasks[0][0].n_atoms} atoms, one per process on {cores} cores, "
+                       f"{steps} NVE steps each (+1 initial force evaluation), {wall:.1f} s wall "
+                       f"(per-process {min(per):.1f}-{max(per):.1f} s), float64 NumPy, one BLAS thread per process; "
+                       f"extrapolated to the {w.n_systems}-system batch")
 
 
 def profile_kernels(api, torch, w, lanes, bin_factor, reps=20, copy_mib=256, group=0):
@@ -416,6 +502,14 @@ def main():
     log(f"batched NVE: {ms_per_step * 1e3:.2f} us/step, {value:.4g} atom-steps/s, rebuilds {r['rebuilds']}")
     roof = force_kernel_roofline(api, torch, r)
     log(f"force kernel: {roof['avg_launch_us']} us/launch, {roof['achieved']} GB/s algorithmic")
+    # the whole step: per atom the fused step kernel reads the position, the row length, the row,
+    # the velocity, the list's reference position and the mass and writes the velocity and the new
+    # position; per system the offsets and the cell (rebuilds excluded: they are amortised)
+    entries = int(r["nl"].n_nbr.sum().item())
+    step_alg = w.n_atoms * (24 + 4 + 48 + 24 + 24 + 8) + 4 * entries + w.n_systems * (16 + 72)
+    step_roof = dict(bound="hbm", alg_bytes_per_step=step_alg, achieved=round(step_alg / (ms_per_step * 1e-3) / 1e9, 1),
+                     peak=HBM_PEAK_GBS, unit="GB/s",
+                     frac=round(step_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -436,6 +530,7 @@ def main():
                    "list_capacity": r["capacity"], "max_list_len": r["max_nbr"], "system_rebuilds": r["rebuilds"],
                    "wall_s": round(r["wall_s"], 4)},
         "roofline": roof,
+        "roofline_whole_step": step_roof,
     }
     if not args.no_plain:
         p = plain_path(api, torch, w, args.plain_steps, args.bin_factor)
@@ -449,10 +544,12 @@ def main():
         out["graph_export"] = graph_export(api, torch, w, args.bin_factor)
         log(f"graph export: {out['graph_export']}")
     if not args.no_adjoint:
-        a = adjoint_throughput(api, torch, 16, args.adjoint_steps, 50)
+        a = adjoint_throughput(api, torch, 16, args.adjoint_steps, 50, plain=not args.no_plain)
         out["adjoint"] = a
         log(f"adjoint: {a['value']:.4g} atom-steps/s")
     if not args.no_fire:
+        out["roofline_copper_forces"] = copper_force_roofline(api, torch)
+        log(f"copper forces: {out['roofline_copper_forces']}")
         out["fire_copper"] = fire_copper(api, torch)
         log(f"copper FIRE: {out['fire_copper']}")
         out["soft_sphere"] = soft_sphere(api, torch)

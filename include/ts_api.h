@@ -166,6 +166,16 @@ int ts_graph_export(const ts_batch *batch, const ts_neighbor_list *nl, double r_
                     int64_t *edge_offsets, int64_t *edge_index, int32_t *edge_shift, double *edge_vec,
                     int64_t capacity, ts_stream_t stream);
 
+/* Pair table of a Lennard-Jones mixture from per-species parameters by the Lorentz-Berthelot
+   rules (the paper's classical potentials, Abstract, applied to several species):
+     epsilon_ab = sqrt(epsilon_a epsilon_b),   sigma_ab = (sigma_a + sigma_b) / 2.
+   Host call (no device work): eps and sigma are HOST arrays of n_species values; writes
+   pp->params[a][b] = (epsilon_ab, sigma_ab, 0) for a, b < n_species, zeroes the other entries and
+   sets pp->n_species; the caller sets kind = TS_LJ, prec, cutoff and shift_energy.
+   Errors: TS_E_INVALID (null pointers, n_species outside 1..TS_MAX_SPECIES, an epsilon negative or
+   not finite, a sigma not positive or not finite). */
+int ts_lorentz_berthelot(int32_t n_species, const double *eps, const double *sigma, ts_pair_params *pp);
+
 /* Energy per system, force per atom and virial per system from the pair potential:
      E_s = 1/2 sum_{(i,j,S)} [phi(r) - shift],  F_i = sum_{(j,S)} (phi'(r)/r) d,
      W_s = -1/2 sum_{(i,j,S)} (phi'(r)/r) d (x) d  (stress = -W/V).
@@ -244,18 +254,28 @@ typedef struct {
   double *scratch;    /* device [S][32] float64 working space */
 } ts_fire_state;
 
-/* Advance every unconverged system by up to n_iter FIRE iterations, then evaluate forces and the
-   convergence test at the final configuration: on completion force/energy/virial (each may be
-   NULL; force is required) describe the final positions and converged[] is current.
-   persistent = 0: each iteration is a few launches over the whole batch (n_iter >= 1).
-   persistent = 1: one launch; workgroups take systems from a device work queue (largest first),
-   keep a system's positions in LDS and iterate it to convergence (n_iter = -1: until converged or
-   max_iter) before taking the next, so a converged system frees its workgroup at once (the
-   in-flight batching of the paper's Section 3, on the device).  Systems above 2048 atoms use the
-   per-iteration path.
+/* Advance every unconverged system by up to n_iter FIRE iterations (n_iter >= 1, or -1 for no
+   per-call budget), then evaluate forces and the convergence test at the final configuration: on
+   completion force/energy/virial (each may be NULL; force is required) describe each system's
+   final positions and converged[] is current.  Like every call, ts_fire_step only enqueues work:
+   it never waits for the device and reads nothing back, so the host learns where each system
+   stands from converged[] and n_iter[] after synchronising.
+   persistent = 0: each iteration is a few launches over the whole batch; the call enqueues
+   min(n_iter, TS_FIRE_TAIL_ITERS) iterations (TS_FIRE_TAIL_ITERS when n_iter = -1).
+   persistent = 1: one persistent launch; workgroups take systems from a device work queue
+   (largest first), keep a system's positions in LDS and iterate it until it converges, reaches
+   max_iter or spends the call's budget, before taking the next, so a converged system frees its
+   workgroup at once (the in-flight batching of the paper's Section 3, on the device).  With more
+   systems than a quarter of the compute units, the launch stops once only that many workgroups
+   are still iterating, and the systems still open continue with the per-iteration kernels for
+   min(n_iter, TS_FIRE_TAIL_ITERS) more iterations (TS_FIRE_TAIL_ITERS when n_iter = -1).  So a
+   call with n_iter = -1, or with n_iter > TS_FIRE_TAIL_ITERS, may return with systems still open
+   (converged = 0, n_iter below max_iter): call again until converged[] or max_iter says stop.
+   Systems above 2048 atoms use the per-iteration path.
    The caller initialises the state (vel = 0, dt = dt_start, alpha = alpha_start, n_pos = 0,
    converged = 0, n_iter = 0, deform = I, deform_vel = 0, ref_cell = cell).
    Errors: TS_E_INVALID, TS_E_UNSUPPORTED. */
+#define TS_FIRE_TAIL_ITERS 256
 int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_fire_config *cfg, ts_neighbor_list *nl,
                  const ts_pair_params *pp, int64_t n_iter, void *force, double *energy, double *virial,
                  int32_t persistent, ts_stream_t stream);

@@ -31,6 +31,7 @@ TS_STATUS_REBUILDS = 2
 TS_STATUS_NONFINITE = 3
 TS_STATUS_SHIFT = 4
 TS_STATUS_WORDS = 8
+TS_FIRE_TAIL_ITERS = 256
 
 KIND_CODES = {"lj": TS_LJ, "morse": TS_MORSE, "soft_sphere": TS_SOFT_SPHERE}
 PREC_CODES = {"f32": TS_PAIR_F32, "f64": TS_PAIR_F64}
@@ -119,6 +120,7 @@ SIGNATURES = {
     "ts_neighbor_build": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), c_int32, c_void_p]),
     "ts_graph_export": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), c_double, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, ctypes.c_int64, c_void_p]),
+    "ts_lorentz_berthelot": (c_int32, [c_int32, c_void_p, c_void_p, POINTER(TsPairParams)]),
     "ts_pair_forces": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_void_p,
                                  c_void_p, c_void_p, c_void_p]),
     "ts_nve_step": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double, c_double,

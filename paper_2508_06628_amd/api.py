@@ -109,17 +109,19 @@ def pair_params(kind: str, params, cutoff: float, shift_energy: bool = False, pr
 
 
 def lorentz_berthelot(eps, sigma) -> np.ndarray:
-    """(S, S, 3) LJ table of a mixture: epsilon_ab = sqrt(epsilon_a epsilon_b),
-    sigma_ab = (sigma_a + sigma_b) / 2 (the Lorentz-Berthelot rules); pass it as ``params``."""
-    e = np.asarray(eps, dtype=np.float64).reshape(-1)
-    s = np.asarray(sigma, dtype=np.float64).reshape(-1)
-    if e.shape != s.shape or e.size < 1 or e.size > N.TS_MAX_SPECIES or np.any(e < 0) or np.any(s <= 0):
+    """(S, S, 3) LJ table of a mixture from per-species epsilon and sigma by the Lorentz-Berthelot
+    rules, as the library's ``ts_lorentz_berthelot`` computes it; pass it as ``params``."""
+    e = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(-1))
+    s = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64).reshape(-1))
+    if e.shape != s.shape:
+        raise ValueError("lorentz_berthelot: one epsilon and one sigma per species")
+    pp = N.TsPairParams()
+    rc = N.lib().ts_lorentz_berthelot(int(e.size), e.ctypes.data, s.ctypes.data, ctypes.byref(pp))
+    if rc != N.TS_OK:
         raise ValueError("lorentz_berthelot: one non-negative epsilon and one positive sigma per species, "
-                         f"at most {N.TS_MAX_SPECIES} species")
-    table = np.zeros((e.size, e.size, 3))
-    table[:, :, 0] = np.sqrt(np.outer(e, e))
-    table[:, :, 1] = 0.5 * (s[:, None] + s[None, :])
-    return table
+                         f"at most {N.TS_MAX_SPECIES} species ({N.lib().ts_strerror(rc).decode()})")
+    full = np.ctypeslib.as_array(pp.params).reshape(N.TS_MAX_SPECIES, N.TS_MAX_SPECIES, 3)
+    return full[:e.size, :e.size].copy()
 
 
 def pair_params_from_spec(spec, prec: str = "f32") -> N.TsPairParams:
@@ -333,6 +335,61 @@ def ts_fire_step(batch, fs: FireState, cfg, nl, pp, n_iter, force, energy=None, 
                                                         ctypes.byref(cfg), ctypes.byref(nl.struct()),
                                                         ctypes.byref(pp), int(n_iter), _p(force), _p(energy),
                                                         _p(virial), 1 if persistent else 0, _stream(stream)))
+
+
+def regrow_neighbor_list(batch: Batch, nl: NeighborList, margin: float = 1.3):
+    """Reallocate the rows for the largest row length the status words recorded (times ``margin``),
+    clear the status words and rebuild every system."""
+    need = int(nl.read_status()[N.TS_STATUS_MAX_NBR])
+    nl._alloc(batch, max(int(math.ceil(need * margin)) + 8, nl.max_nbr + 8))
+    ts_neighbor_build(batch, nl, force=True)
+
+
+def nve_run(batch: Batch, nl: NeighborList, pp, dt, accel, n_steps, force, chunk=100, use_graph=True, margin=1.3,
+            max_replays=4):
+    """``n_steps`` of ``ts_nve_step`` in calls of ``chunk`` steps with recovery from list overflow:
+    after each call the host reads the status words; if a row was truncated, the state from before
+    the call is restored, the list is regrown (``regrow_neighbor_list``) and rebuilt, the forces are
+    re-evaluated and the call is replayed.  Non-finite positions or dropped image shifts raise.
+    Returns the number of replays."""
+    replays = 0
+    done = 0
+    nl.status.zero_()
+    while done < n_steps:
+        k = min(chunk, n_steps - done)
+        saved = (batch.pos.clone(), batch.vel.clone(), batch.cell.clone())
+        ts_nve_step(batch, nl, pp, dt, accel, k, force, use_graph=use_graph)
+        st = nl.read_status()
+        if st[N.TS_STATUS_NONFINITE] or st[N.TS_STATUS_SHIFT]:
+            raise RuntimeError(f"nve_run: neighbor list status {st.tolist()}")
+        if st[N.TS_STATUS_OVERFLOW]:
+            if replays >= max_replays:
+                raise RuntimeError("nve_run: list overflow persists after regrowth")
+            replays += 1
+            batch.pos.copy_(saved[0])
+            batch.vel.copy_(saved[1])
+            batch.cell.copy_(saved[2])
+            regrow_neighbor_list(batch, nl, margin)
+            ts_pair_forces(batch, nl, pp, force)
+            nl.status.zero_()
+            continue
+        done += k
+    return replays
+
+
+def fire_relax(batch, fs: FireState, cfg, nl, pp, force, energy=None, virial=None, persistent=True,
+               max_calls=100000, stream=None):
+    """Repeat ``ts_fire_step(n_iter=-1)`` until every system has converged or reached max_iter: each
+    call only enqueues work (its persistent launch and a bounded tail), so the host reads the
+    per-system flags between calls.  Returns the number of calls."""
+    n_calls = 0
+    while n_calls < max_calls:
+        ts_fire_step(batch, fs, cfg, nl, pp, -1, force, energy, virial, persistent, stream)
+        n_calls += 1
+        open_ = (fs.converged == 0) & (fs.n_iter < int(cfg.max_iter))
+        if not bool(open_.any().item()):
+            break
+    return n_calls
 
 
 def ts_pair_adjoint(batch, nl, pp, dt_drift, w_kick, accel, adj_pos, adj_vel, adj_params=None, stream=None):

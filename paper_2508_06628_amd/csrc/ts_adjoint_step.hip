@@ -40,6 +40,7 @@ struct AdjStepArgs {
   double dt_drift, w, accel;
   int32_t *flag_next, *flag_clear, *list_next, *count_next, *count_clear;
   double r_list, skin;
+  int n_sys;
 };
 
 // Validity of the list for positions `pos` (compact stride n): flag systems for a rebuild.
@@ -58,8 +59,10 @@ __global__ void k_list_check(StepArgs a, const double *pos, int64_t n) {
   if (list_invalid(r, a.ref_pos, a.st_vel, i, a.cell + 9 * (int64_t)s, a.ref_cell + 9 * (int64_t)s, a.skin,
                    a.r_list) &&
       __hip_atomic_load(&a.flag_next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-      atomicExch(&a.flag_next[s], 1) == 0)
-    a.list_next[atomicAdd(a.count_next, 1)] = s;
+      atomicExch(&a.flag_next[s], 1) == 0) {
+    const int q = atomicAdd(a.count_next, 1);
+    if (q < (int)a.n_atoms) a.list_next[q] = s;  // a.n_atoms: number of systems (see above)
+  }
 }
 
 template <int KIND, typename T, int TL, bool SINGLE>
@@ -72,6 +75,12 @@ __global__ void __launch_bounds__(256) k_adj_step(PairTable tab, AdjStepArgs a) 
   const int64_t a0 = a.offs[s];
   const int ns = (int)(a.offs[s + 1] - a0);
   const int first = blockIdx.x * APB;
+  // flags and list count of the position after next are cleared ahead of every early exit (an
+  // empty system still clears its flag, and system 0 the count, whatever its size)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.flag_clear[s] = 0;
+    if (s == 0) *a.count_clear = 0;
+  }
   if (first >= ns) return;
   const int tid = threadIdx.x, grp = tid / TL, lane = tid % TL;
   const int li = first + grp;
@@ -173,13 +182,11 @@ __global__ void __launch_bounds__(256) k_adj_step(PairTable tab, AdjStepArgs a) 
       // (a plain read first: the exchange of every atom over the bound would serialise on one word)
       if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list) &&
           __hip_atomic_load(&a.flag_next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-          atomicExch(&a.flag_next[s], 1) == 0)
-        a.list_next[atomicAdd(a.count_next, 1)] = s;
+          atomicExch(&a.flag_next[s], 1) == 0) {
+        const int q = atomicAdd(a.count_next, 1);
+        if (q < a.n_sys) a.list_next[q] = s;
+      }
     }
-  }
-  if (blockIdx.x == 0 && tid == 0) {
-    a.flag_clear[s] = 0;
-    if (s == 0) *a.count_clear = 0;
   }
   if (a.adj_params) {
     // workgroup sums go to the system's slot (atomics shared by the workgroups of one system only:
@@ -293,6 +300,7 @@ static int adjoint_segment(const ts_batch *b, ts_neighbor_list *nl, const ts_pai
   }
   a.r_list = r.r_list;
   a.skin = r.skin;
+  a.n_sys = (int)S;
   for (int p = 0; p < P; ++p) {
     const int m = n_steps - p;
     const bool first_kick = top && p == 0;

@@ -103,6 +103,22 @@ PairTable make_table(const ts_pair_params *pp) {
 
 }  // namespace ts
 
+extern "C" int ts_lorentz_berthelot(int32_t n_species, const double *eps, const double *sigma, ts_pair_params *pp) {
+  TS_CHECK_ARG(eps && sigma && pp && n_species >= 1 && n_species <= TS_MAX_SPECIES);
+  for (int a = 0; a < n_species; ++a)
+    TS_CHECK_ARG(std::isfinite(eps[a]) && eps[a] >= 0.0 && std::isfinite(sigma[a]) && sigma[a] > 0.0);
+  for (int a = 0; a < TS_MAX_SPECIES; ++a)
+    for (int b = 0; b < TS_MAX_SPECIES; ++b) {
+      double *p = pp->params[a][b];
+      const bool in = a < n_species && b < n_species;
+      p[0] = in ? std::sqrt(eps[a] * eps[b]) : 0.0;
+      p[1] = in ? 0.5 * (sigma[a] + sigma[b]) : 0.0;
+      p[2] = 0.0;
+    }
+  pp->n_species = n_species;
+  return TS_OK;
+}
+
 extern "C" const char *ts_strerror(int status) {
   switch (status) {
     case TS_OK: return "ok";

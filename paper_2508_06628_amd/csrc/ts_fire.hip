@@ -57,7 +57,6 @@ __device__ inline double block_max(double v, double *sh) {
 // The slot of chunk c of system s is s + floor((a0_s + kFireChunk c) / kFireChunk): unique, and at
 // most S + N / kFireChunk + 1 slots of 4 doubles.
 constexpr int kFireChunk = 256;
-constexpr int64_t kFireTailChunk = 32;  // tail iterations between two host checks
 
 __device__ inline int64_t fire_slot(int s, int64_t a0, int c) { return s + (a0 + (int64_t)kFireChunk * c) / kFireChunk; }
 
@@ -274,21 +273,6 @@ static int launch_fire_update(const FireArgs &fa, bool cell, int final_check, in
   return TS_OK;
 }
 
-// Systems still open (not converged, below max_iter and below this call's budget) -> *out.
-__global__ void __launch_bounds__(256) k_fire_open(FireArgs a, int64_t n_sys, int32_t *out) {
-  __shared__ int32_t tot[4];
-  int32_t c = 0;
-  for (int64_t s = threadIdx.x; s < n_sys; s += blockDim.x) {
-    const bool budget_left = !a.iter_start || a.budget < 0 || a.n_iter[s] - a.iter_start[s] < a.budget;
-    c += (!a.converged[s] && a.n_iter[s] < a.cfg.max_iter && budget_left) ? 1 : 0;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
-  if (threadIdx.x % kWave == 0) tot[threadIdx.x / kWave] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) *out = tot[0] + tot[1] + tot[2] + tot[3];
-}
-
 FireArgs make_fire_args(const ts_batch *b, const ts_fire_state *fs, const ts_fire_config *cfg, void *force,
                         double *virial) {
   FireArgs fa;
@@ -327,13 +311,14 @@ static int fire_iterations(const ts_batch *batch, const ts_fire_state *fs, const
   const NlWork w = nl_work(nl->workspace, batch->n_atoms, S);
   double *part = w.adj_alt;
   double *coef = fs->scratch + 9 * S;
+  // energy and virial are evaluated at every iteration: a system that converges (and is frozen)
+  // before the last one keeps the values of its final configuration
+  const bool ev = cell || energy || virial;
   for (int64_t it = 0; it <= n_iter; ++it) {
     const bool last = it == n_iter;
     int rc = nl_update(batch, nl, 0, max_atoms, st);
     if (rc != TS_OK) return rc;
-    double *e = last ? energy : nullptr;
-    const bool ev = cell || (last && (energy || virial));
-    rc = launch_forces(make_force_args(batch, nl, force, e, ev ? fa.virial : nullptr, fs->converged), S, tab,
+    rc = launch_forces(make_force_args(batch, nl, force, energy, ev ? fa.virial : nullptr, fs->converged), S, tab,
                        pp->prec, ev, st);
     if (rc != TS_OK) return rc;
     rc = pp->prec == TS_PAIR_F32 ? launch_fire_update<float>(fa, cell, last ? 1 : 0, S, max_atoms, part, coef, st)
@@ -351,7 +336,7 @@ extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_f
   int64_t max_atoms = 0;
   int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, true);
   if (rc != TS_OK) return rc;
-  TS_CHECK_ARG(fs && cfg && force && (n_iter >= 1 || (persistent && n_iter == -1)));
+  TS_CHECK_ARG(fs && cfg && force && (n_iter >= 1 || n_iter == -1));
   TS_CHECK_ARG(fs->dt && fs->alpha && fs->n_pos && fs->converged && fs->n_iter && fs->scratch);
   TS_CHECK_ARG(cfg->fmax > 0.0 && cfg->dt_start > 0.0 && cfg->dt_max > 0.0 && cfg->f_dec > 0.0 && cfg->f_inc > 0.0);
   const bool cell = cfg->relax_cell != 0;
@@ -364,6 +349,8 @@ extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_f
   const int64_t S = batch->n_systems;
   double *vir = virial ? virial : fs->scratch;  // scratch holds [S][9] when the caller wants no virial
   ts::FireArgs fa = ts::make_fire_args(batch, fs, cfg, force, vir);
+  // iterations of the per-iteration kernels enqueued by one call when the budget is open or larger
+  const int64_t tail = (n_iter < 0 || n_iter > TS_FIRE_TAIL_ITERS) ? TS_FIRE_TAIL_ITERS : n_iter;
   if (persistent && max_atoms <= ts::kLdsMaxAtoms) {
     // n_iter at the start of the call, for the per-call budget of the tail (scratch slots 31 S..32 S)
     int64_t *iter_start = reinterpret_cast<int64_t *>(fs->scratch + 31 * S);
@@ -373,23 +360,14 @@ extern "C" int ts_fire_step(const ts_batch *batch, ts_fire_state *fs, const ts_f
     if (rc != TS_OK || !handed_off) return rc;
     // the tail: systems still iterating when the persistent launch stopped (it stops once most of
     // its workgroups are idle) continue with the per-iteration kernels, which spread every system
-    // over many workgroups; the host checks after each chunk whether any system is still open
+    // over many workgroups.  A fixed number of iterations is enqueued (the host reads nothing);
+    // each one leaves converged systems, systems at max_iter and systems whose budget for this
+    // call is spent untouched.
     fa.iter_start = iter_start;
     fa.budget = n_iter;
-    int32_t *d_open = reinterpret_cast<int32_t *>(ts::nl_work(nl->workspace, batch->n_atoms, S).flags3) + 6 * S + 2;
-    for (;;) {
-      hipLaunchKernelGGL(ts::k_fire_open, dim3(1), dim3(256), 0, st, fa, S, d_open);
-      TS_LAUNCH_CHECK();
-      int32_t open = 0;
-      TS_HIP(hipMemcpyAsync(&open, d_open, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      TS_HIP(hipStreamSynchronize(st));
-      if (open == 0) return TS_OK;
-      rc = ts::fire_iterations(batch, fs, cfg, nl, pp, fa, ts::kFireTailChunk, force, energy, virial, max_atoms, st);
-      if (rc != TS_OK) return rc;
-    }
+    return ts::fire_iterations(batch, fs, cfg, nl, pp, fa, tail, force, energy, virial, max_atoms, st);
   }
-  TS_CHECK_ARG(n_iter >= 1);
-  rc = ts::fire_iterations(batch, fs, cfg, nl, pp, fa, n_iter, force, energy, virial, max_atoms, st);
+  rc = ts::fire_iterations(batch, fs, cfg, nl, pp, fa, tail, force, energy, virial, max_atoms, st);
   if (rc != TS_OK) return rc;
   return TS_OK;
 }

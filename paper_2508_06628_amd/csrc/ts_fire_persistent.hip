@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(kPT) k_fire_persistent(PairTable tab, FirePArg
         // float32 prefilter on wrapped fractional coordinates ahead of the exact float64 test
         const bool wide = sh[18] < 0.5 - 1e-3 && sh[19] < 0.5 - 1e-3 && sh[20] < 0.5 - 1e-3;
         if (wide) {
-          float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns);
+          float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns + (ns & 1));  // 16-byte aligned
           for (int k = tid; k < ns; k += kPT) {
             const double x = lx[k], y = ly[k], z = lz[k];
             const double f0 = x * sh[9] + y * sh[12] + z * sh[15], f1 = x * sh[10] + y * sh[13] + z * sh[16],
@@ -633,7 +633,7 @@ int fire_persistent(const ts_batch *b, const ts_fire_state *fs, const ts_fire_co
   if (handed_off) *handed_off = a.idle_limit > 0;
   // positions (3 x float64), wrapped fractional coordinates of the rebuild (float4) and the
   // rebuild's survivor queues
-  const size_t shm = (size_t)(3 * sizeof(double) + sizeof(float4)) * (size_t)max_atoms +
+  const size_t shm = (size_t)(3 * sizeof(double) + sizeof(float4)) * (size_t)max_atoms + sizeof(double) +
                      sizeof(int) * kPSurv * kPW;
   const PairTable t = make_table(pp);
   const dim3 g((unsigned)grid);

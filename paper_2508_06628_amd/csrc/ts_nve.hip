@@ -154,6 +154,7 @@ int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable 
   a.half_dt = 0.5 * dt;
   a.dt = dt;
   a.accel = accel;
+  a.n_sys = (int)S;
   if (lang) {
     a.lang = *lang;
     a.lang_adv = n_steps;

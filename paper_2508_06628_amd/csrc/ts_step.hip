@@ -25,7 +25,12 @@ namespace ts {
 // is visibly set (same-address atomics serialise), and the exchange still decides who appends.
 __device__ inline void flag_system(const StepArgs &a, int s) {
   if (__hip_atomic_load(&a.flag_next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  if (atomicExch(&a.flag_next[s], 1) == 0) a.list_next[atomicAdd(a.count_next, 1)] = s;
+  if (atomicExch(&a.flag_next[s], 1) == 0) {
+    // each system enters a list once per step (the exchange above), so the slot is below n_sys
+    // whenever the count was cleared; the bound keeps a stale count from writing past the list
+    const int q = atomicAdd(a.count_next, 1);
+    if (q < a.n_sys) a.list_next[q] = s;
+  }
 }
 
 template <int KIND, typename T, int TL, int MODE>
@@ -44,6 +49,13 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   // address derived from it into vector registers)
   const int s = __builtin_amdgcn_readfirstlane(wg / a.chunks);
   const int chunk = __builtin_amdgcn_readfirstlane(wg - s * a.chunks);
+  // the flags and the list count of step n+2 (those of step n-1, consumed by the rebuild before
+  // step n-1) are cleared here, ahead of every early exit: an empty system still clears its flag,
+  // and workgroup 0 (system 0, chunk 0) the count, whatever the size of system 0
+  if (MID && chunk == 0 && threadIdx.x == 0) {
+    a.flag_clear[s] = 0;
+    if (s == 0) *a.count_clear = 0;
+  }
   const int64_t a0 = a.offs[s];
   const int ns = (int)(a.offs[s + 1] - a0);
   const int first = chunk * APB * a.rounds;
@@ -280,10 +292,6 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
       }
     }
   }  // rounds
-  if (MID && chunk == 0 && tid == 0) {
-    a.flag_clear[s] = 0;
-    if (s == 0) *a.count_clear = 0;
-  }
   if (EV && (a.epot || a.virial)) {
     // every lane of the block belongs to system s
     const double ev = wave_sum(0.5 * e);
@@ -325,7 +333,8 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
   // is read speculatively: the list has room for every system)
   const int q0 = blockIdx.x / chunks_per_sys;
   const int s_spec = q0 < a.n_sys ? a.list_cur[q0] : 0;
-  const int n_flag = *a.count_cur;
+  const int n_cnt = *a.count_cur;
+  const int n_flag = n_cnt < a.n_sys ? n_cnt : a.n_sys;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const double rl2 = a.r_list * a.r_list;
   const int64_t st = a.st_vel;
@@ -366,11 +375,11 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     // of reach), and the float32 prefilter on wrapped fractional coordinates below is safe
     const bool wide = re0 < 0.5 - 1e-3 && re1 < 0.5 - 1e-3 && re2 < 0.5 - 1e-3;
     __syncthreads();  // the previous chunk's readers are done with lds
-    // LDS: float64 positions [3][ns]; wide cells also float4 wrapped fractional coordinates [ns] and
-    // the wavefronts' survivor queues
+    // LDS: float64 positions [3][ns]; wide cells also float4 wrapped fractional coordinates [ns]
+    // (16-byte aligned: one padding double when ns is odd) and the wavefronts' survivor queues
     double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
-    float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns);
-    int *surv = reinterpret_cast<int *>(lds + 5 * ns) + wave * kSurvCap;
+    float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns + (ns & 1));
+    int *surv = reinterpret_cast<int *>(sf + ns) + wave * kSurvCap;
     for (int k = threadIdx.x; k < ns; k += blockDim.x) {
       const double x = pin[a0 + k], y = pin[a.st_in + a0 + k], z = pin[2 * a.st_in + a0 + k];
       lx[k] = x;
@@ -564,8 +573,9 @@ int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStrea
   const int chunks = (int)ceil_div(max_atoms, kRebuildWaves);
   const int64_t work = n_sys * chunks;
   const unsigned grid = (unsigned)(work < 2048 ? work : 2048);
-  // float64 positions, float4 fractional coordinates and the survivor queues (wide cells)
-  const size_t shm = (size_t)5 * sizeof(double) * (size_t)max_atoms + sizeof(int) * kSurvCap * kRebuildWaves;
+  // float64 positions, float4 fractional coordinates (after one alignment double) and the
+  // survivor queues (wide cells)
+  const size_t shm = (size_t)(5 * max_atoms + 1) * sizeof(double) + sizeof(int) * kSurvCap * kRebuildWaves;
   StepArgs b = a;
   b.n_sys = (int)n_sys;
   hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, b, chunks);

@@ -35,8 +35,9 @@ class TrajectoryRDF:
     """Loss L(eps, sigma, r_0) of one LJ batch; single-species parameters (eps, sigma)."""
 
     def __init__(self, workload, n_steps: int, checkpoint_every: int = 50, prec: str = "f32",
-                 rdf: RdfSpec = RdfSpec(), skin: float = 0.3, bin_factor: int = 2):
+                 rdf: RdfSpec = RdfSpec(), skin: float = 0.3, bin_factor: int = 2, use_graph: bool = True):
         self.w = workload
+        self.use_graph = bool(use_graph)
         self.n_steps = int(n_steps)
         self.K = int(checkpoint_every)
         self.prec = prec
@@ -83,12 +84,21 @@ class TrajectoryRDF:
             if keep_checkpoints:
                 self.checkpoints.append((self.batch.pos.clone(), self.batch.vel.clone()))
             k = min(self.K, self.n_steps - done)
-            api.ts_nve_step(self.batch, self.nl, pp, self.w.dt, self.w.accel, k, self.force, use_graph=True)
+            api.ts_nve_step(self.batch, self.nl, pp, self.w.dt, self.w.accel, k, self.force, use_graph=self.use_graph)
             done += k
         api.ts_neighbor_build(self.batch, self.nl_rdf, force=True)
         r = self.rdf
         api.ts_rdf_smeared(self.batch, self.nl_rdf, r.n_bins, r.r_end, r.sigma, r.r_max, self.g)
         return self.g
+
+    def check_status(self):
+        """Raise if a neighbor list overflowed, met a non-finite position or dropped an image shift
+        in the calls so far (a truncated list would give wrong forces and gradients); clears them."""
+        for name, nl in (("trajectory", self.nl), ("rdf", self.nl_rdf)):
+            st = nl.read_status()
+            if st[1] or st[3] or st[4]:
+                raise RuntimeError(f"{name} neighbor list status {st.tolist()} (overflow, non-finite, shift)")
+            nl.status.zero_()
 
     def set_target(self, g_target: torch.Tensor):
         self.target.copy_(g_target)
@@ -125,8 +135,9 @@ class TrajectoryRDF:
             b.vel.copy_(v0)
             api.ts_neighbor_build(b, self.nl, force=True)
             api.ts_pair_forces(b, self.nl, pp, self.force)
-            api.ts_nve_record(b, self.nl, pp, dt, accel, k, self.force, self._traj)
-            api.ts_adjoint_segment(b, self.nl, pp, self._traj, k, dt, accel, seg == n_seg - 1, seg == 0, lr, lv, tb)
+            api.ts_nve_record(b, self.nl, pp, dt, accel, k, self.force, self._traj, use_graph=self.use_graph)
+            api.ts_adjoint_segment(b, self.nl, pp, self._traj, k, dt, accel, seg == n_seg - 1, seg == 0, lr, lv, tb,
+                                   use_graph=self.use_graph)
         grads = tb.cpu().numpy()
         return float(grads[0]), float(grads[1]), lr
 

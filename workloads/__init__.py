@@ -27,6 +27,8 @@ from .generators import (  # noqa: F401
     argon_adjoint_batch,
     soft_sphere_jamming_batch,
     random_small_batch,
+    narrow_triclinic_batch,
+    insert_empty_systems,
     ARGON_MASS,
     COPPER_MASS,
 )

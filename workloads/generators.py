@@ -364,3 +364,58 @@ def random_small_batch(seed: int, n_systems: int = 3, n_range=(2, 40), kind: str
         systems.append(dict(pos=pos, vel=vel, mass=mass, species=species, cell=cell))
     return concat_systems(f"random_{kind}_{seed}", systems, pot, skin=skin, dt=0.002, n_steps=10,
                           pair_prec=pair_prec, accel=1.0, kinetic_factor=1.0)
+
+
+def narrow_triclinic_batch(seed: int, n_systems: int = 3, n_range=(2100, 2600), narrow: float = 4.2,
+                           density: float = 0.85, tilt: float = 0.25, unwrap_spread: int = 2,
+                           empty_first: bool = False) -> Workload:
+    """Large random LJ systems (reduced units, cutoff 2.5) in sheared cells that are narrow along the
+    first lattice direction (perpendicular width near ``narrow``, below twice a list radius of 2.8,
+    so several images of one pair are in range) and wide along the other two; uniform random
+    fractional positions, a third of the atoms displaced by whole lattice vectors up to
+    ``unwrap_spread`` (positions not wrapped).  ``empty_first`` prepends a system with no atoms."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    p = np.zeros((1, 1, 3))
+    p[0, 0] = (1.0, 1.0, 0.0)
+    pot = PotentialSpec("lj", p, 2.5, True)
+    systems = []
+    if empty_first:
+        systems.append(dict(pos=np.zeros((0, 3)), vel=np.zeros((0, 3)), mass=np.zeros(0),
+                            species=np.zeros(0, np.int32), cell=np.diag([narrow, 20.0, 20.0])))
+    for _ in range(n_systems):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        side = np.sqrt(n / (density * narrow))
+        shear = np.eye(3)
+        shear[np.triu_indices(3, 1)] = rng.uniform(-tilt, tilt, size=3)
+        shear[np.tril_indices(3, -1)] = rng.uniform(-0.5 * tilt, 0.5 * tilt, size=3)
+        cell = np.diag([narrow, side, side]) @ shear
+        frac = rng.uniform(0.0, 1.0, size=(n, 3))
+        pos = frac @ cell
+        moved = rng.random(n) < 1.0 / 3.0
+        k = rng.integers(-unwrap_spread, unwrap_spread + 1, size=(n, 3))
+        pos[moved] += k[moved] @ cell
+        systems.append(dict(pos=pos, vel=np.zeros((n, 3)), mass=np.ones(n), species=np.zeros(n, np.int32),
+                            cell=cell))
+    return concat_systems(f"narrow_triclinic_{seed}", systems, pot, skin=0.3, dt=0.002, n_steps=10,
+                          pair_prec="f64", accel=1.0, kinetic_factor=1.0)
+
+
+def insert_empty_systems(w: Workload, at) -> Workload:
+    """The workload with a system of no atoms inserted before each listed system index (``at``
+    refers to the original numbering; ``len(systems)`` appends at the end).  The empty systems get
+    the cell of the system they precede (or of the last one)."""
+    at = sorted(int(a) for a in at)
+    counts = list(np.diff(w.sys_offsets))
+    cells = list(w.cell)
+    new_counts, new_cells = [], []
+    for s in range(w.n_systems + 1):
+        for a in at:
+            if a == s:
+                new_counts.append(0)
+                new_cells.append(cells[min(s, w.n_systems - 1)])
+        if s < w.n_systems:
+            new_counts.append(counts[s])
+            new_cells.append(cells[s])
+    offs = np.concatenate([[0], np.cumsum(new_counts)]).astype(np.int64)
+    return dataclasses.replace(w, name=f"{w.name}+{len(at)} empty", sys_offsets=offs,
+                               cell=np.stack(new_cells).astype(np.float64), extra=dict(w.extra))

@@ -99,7 +99,7 @@ def system_hvp(pos, cell, species, potential, u):
     """(J u)_i with J = dF/dr of one system."""
     p, sp = _pair_terms(pos, cell, species, potential)
     r = np.sqrt(p["r2"])
-    _, d1, d2 = _pot.phi_and_derivs(potential.kind, sp, r)
+    _, d1, d2 = _pot.phi_and_derivs(potential.kind, sp, r, potential.cutoff)
     dhat = p["d"] / r[:, None]
     du = u[p["j"]] - u[p["i"]]
     proj = (dhat * du).sum(axis=1)
@@ -113,7 +113,7 @@ def system_param_vjp(pos, cell, species, potential, u):
     """sum_i u_i . dF_i/dtheta, accumulated per (s_i, s_j, slot)."""
     p, sp = _pair_terms(pos, cell, species, potential)
     r = np.sqrt(p["r2"])
-    dg = _pot.dg_dparams(potential.kind, sp, r)
+    dg = _pot.dg_dparams(potential.kind, sp, r, potential.cutoff)
     ud = (u[p["i"]] * p["d"]).sum(axis=1)
     ns = potential.params.shape[0]
     out = np.zeros((ns, ns, 3))

@@ -26,7 +26,7 @@ def system_efw(pos, cell, species, params, kind, cutoff, shift, rows=None):
     m = _pot.in_range(kind, sp, p["r2"], cutoff)
     i, d, r2, sp = p["i"][m], p["d"][m], p["r2"][m], sp[m]
     r = np.sqrt(r2)
-    phi, d1, _ = _pot.phi_and_derivs(kind, sp, r)
+    phi, d1, _ = _pot.phi_and_derivs(kind, sp, r, cutoff)
     phi = phi - _pot.energy_shift(kind, sp, cutoff, shift)
     g = d1 / r
     f = g[:, None] * d
@@ -60,7 +60,7 @@ def pair_magnitude_sums(pos, cell, species, params, kind, cutoff, rows=None):
     m = _pot.in_range(kind, sp, p["r2"], cutoff)
     i, r2, sp = p["i"][m], p["r2"][m], sp[m]
     r = np.sqrt(r2)
-    phi, d1, _ = _pot.phi_and_derivs(kind, sp, r)
+    phi, d1, _ = _pot.phi_and_derivs(kind, sp, r, cutoff)
     A = np.zeros(n)
     np.add.at(A, i, np.abs(d1))
     return A, 0.5 * np.abs(phi).sum(), 0.5 * np.abs(r * d1).sum()

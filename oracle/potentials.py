@@ -10,18 +10,37 @@ Per species pair the parameter triple p = params[s_i, s_j] is
 A pair interacts when r < r_c (and, for the soft sphere, also r < sigma_ij).  With the energy
 shift, phi(r) - phi(r_c) is used inside the cutoff (forces unchanged).
 
+Shifted-force kinds ``lj_sf`` and ``morse_sf`` (the textbook smooth truncation; the paper's
+differentiable-simulation use, Section 2, benefits from a force that vanishes continuously at the
+cutoff): with phi the plain form,
+    phi_sf(r) = phi(r) - phi(r_c) - (r - r_c) phi'(r_c)   for r < r_c,
+so phi_sf(r_c) = 0 and phi_sf'(r_c) = 0; phi_sf'' = phi''.
+
 Every function takes arrays of r and of parameter triples (one per pair) and returns float64.
 """
 from __future__ import annotations
 
 import numpy as np
 
-KINDS = ("lj", "morse", "soft_sphere")
+KINDS = ("lj", "morse", "soft_sphere", "lj_sf", "morse_sf")
 
 
-def phi_and_derivs(kind: str, p: np.ndarray, r: np.ndarray):
-    """phi(r), phi'(r), phi''(r) for parameter rows p (P, 3) and distances r (P,)."""
+def base_kind(kind: str) -> str:
+    """The plain form a shifted-force kind truncates."""
+    return kind[:-3] if kind.endswith("_sf") else kind
+
+
+def phi_and_derivs(kind: str, p: np.ndarray, r: np.ndarray, cutoff: float = None):
+    """phi(r), phi'(r), phi''(r) for parameter rows p (P, 3) and distances r (P,).  Shifted-force
+    kinds need the cutoff r_c."""
     r = np.asarray(r, dtype=np.float64)
+    if kind.endswith("_sf"):
+        if cutoff is None:
+            raise ValueError(f"{kind} needs the cutoff")
+        base = base_kind(kind)
+        phi, d1, d2 = phi_and_derivs(base, p, r)
+        phi_c, d1_c, _ = phi_and_derivs(base, p, np.full(r.shape[0], float(cutoff)))
+        return phi - phi_c - (r - cutoff) * d1_c, d1 - d1_c, d2
     if kind == "lj":
         eps, sig = p[:, 0], p[:, 1]
         sr6 = (sig / r) ** 6
@@ -47,6 +66,7 @@ def phi_and_derivs(kind: str, p: np.ndarray, r: np.ndarray):
 
 
 def in_range(kind: str, p: np.ndarray, r2: np.ndarray, cutoff: float) -> np.ndarray:
+    kind = base_kind(kind)
     """Interaction mask, decided in float64 on squared distances: r^2 < r_c^2 (and r^2 < sigma_ij^2
     for the soft sphere)."""
     m = r2 < cutoff * cutoff
@@ -56,16 +76,23 @@ def in_range(kind: str, p: np.ndarray, r2: np.ndarray, cutoff: float) -> np.ndar
 
 
 def energy_shift(kind: str, p: np.ndarray, cutoff: float, shift: bool) -> np.ndarray:
-    """phi(r_c) per parameter row when the energy is shifted, else zeros (soft sphere: zero)."""
-    if not shift or kind == "soft_sphere":
+    """phi(r_c) per parameter row when the energy is shifted, else zeros (soft sphere and the
+    shifted-force kinds, which vanish at r_c by construction: zero)."""
+    if not shift or kind == "soft_sphere" or kind.endswith("_sf"):
         return np.zeros(p.shape[0])
     return phi_and_derivs(kind, p, np.full(p.shape[0], cutoff))[0]
 
 
-def dg_dparams(kind: str, p: np.ndarray, r: np.ndarray) -> np.ndarray:
+def dg_dparams(kind: str, p: np.ndarray, r: np.ndarray, cutoff: float = None) -> np.ndarray:
     """Derivatives of g(r) = phi'(r) / r with respect to the three parameter slots, shape (P, 3).
-    The pair force on i is g(r) d, so these give the pair-force parameter derivatives."""
+    The pair force on i is g(r) d, so these give the pair-force parameter derivatives.  For a
+    shifted-force kind g_sf(r) = g(r) - phi'(r_c) / r and phi'(r_c) = r_c g(r_c), so
+    dg_sf/dtheta = dg/dtheta (r) - (r_c / r) dg/dtheta (r_c)."""
     r = np.asarray(r, dtype=np.float64)
+    if kind.endswith("_sf"):
+        base = base_kind(kind)
+        at_c = dg_dparams(base, p, np.full(r.shape[0], float(cutoff)))
+        return dg_dparams(base, p, r) - (cutoff / r)[:, None] * at_c
     out = np.zeros((r.shape[0], 3))
     if kind == "lj":
         eps, sig = p[:, 0], p[:, 1]

@@ -50,7 +50,7 @@ typedef enum {
   TS_E_HIP = -4          /* the HIP runtime reported an error (launch, graph, device query) */
 } ts_status;
 
-typedef enum { TS_LJ = 0, TS_MORSE = 1, TS_SOFT_SPHERE = 2 } ts_potential;
+typedef enum { TS_LJ = 0, TS_MORSE = 1, TS_SOFT_SPHERE = 2, TS_LJ_SF = 3, TS_MORSE_SF = 4 } ts_potential;
 typedef enum { TS_PAIR_F32 = 0, TS_PAIR_F64 = 1 } ts_pair_prec;
 
 #define TS_MAX_SPECIES 4
@@ -86,8 +86,12 @@ typedef struct {
      TS_LJ:          (epsilon, sigma, unused)   phi = 4 eps ((sigma/r)^12 - (sigma/r)^6)
      TS_MORSE:       (D, alpha, r0)             phi = D (exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0)))
      TS_SOFT_SPHERE: (epsilon, sigma_ij, unused) phi = eps/2 (1 - r/sigma_ij)^2 for r < sigma_ij
+     TS_LJ_SF, TS_MORSE_SF: the LJ / Morse parameters, shifted-force truncation
+                     phi_sf(r) = phi(r) - phi(r_c) - (r - r_c) phi'(r_c): energy and force both go
+                     to zero continuously at the cutoff (smooth trajectory gradients)
    A pair interacts when r^2 < cutoff^2 (decided in float64), and for the soft sphere also
-   r^2 < sigma_ij^2.  shift_energy = 1 subtracts phi(cutoff) inside the cutoff (LJ, Morse).
+   r^2 < sigma_ij^2.  shift_energy = 1 subtracts phi(cutoff) inside the cutoff (LJ, Morse; the
+   shifted-force kinds ignore it: they vanish at the cutoff by construction).
    prec = TS_PAIR_F32: the pair vector and the cutoff test are float64, the pair function is
    evaluated in float32 (soft sphere: overlap 1 - r/sigma_ij in float64), and forces, energies,
    virials are accumulated in float64; forces are stored as float32.  TS_PAIR_F64: all float64. */

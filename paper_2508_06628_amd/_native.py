@@ -19,7 +19,7 @@ TS_E_UNSUPPORTED = -2
 TS_E_CAPACITY = -3
 TS_E_HIP = -4
 
-TS_LJ, TS_MORSE, TS_SOFT_SPHERE = 0, 1, 2
+TS_LJ, TS_MORSE, TS_SOFT_SPHERE, TS_LJ_SF, TS_MORSE_SF = 0, 1, 2, 3, 4
 TS_PAIR_F32, TS_PAIR_F64 = 0, 1
 TS_MAX_SPECIES = 4
 TS_MAX_SYSTEM_ATOMS = 131072
@@ -33,7 +33,8 @@ TS_STATUS_SHIFT = 4
 TS_STATUS_WORDS = 8
 TS_FIRE_TAIL_ITERS = 256
 
-KIND_CODES = {"lj": TS_LJ, "morse": TS_MORSE, "soft_sphere": TS_SOFT_SPHERE}
+KIND_CODES = {"lj": TS_LJ, "morse": TS_MORSE, "soft_sphere": TS_SOFT_SPHERE, "lj_sf": TS_LJ_SF,
+              "morse_sf": TS_MORSE_SF}
 PREC_CODES = {"f32": TS_PAIR_F32, "f64": TS_PAIR_F64}
 
 

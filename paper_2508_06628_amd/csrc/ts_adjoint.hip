@@ -382,15 +382,11 @@ extern "C" int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl
   }
   const ts::PairTable t = ts::make_table(pp);
   const bool single = t.n_species == 1 || batch->species == nullptr;
-  if (pp->prec == TS_PAIR_F32) {
-    if (t.kind == TS_LJ) ts::launch_vjp<TS_LJ, float>(a, t, single, st);
-    else if (t.kind == TS_MORSE) ts::launch_vjp<TS_MORSE, float>(a, t, single, st);
-    else ts::launch_vjp<TS_SOFT_SPHERE, float>(a, t, single, st);
-  } else {
-    if (t.kind == TS_LJ) ts::launch_vjp<TS_LJ, double>(a, t, single, st);
-    else if (t.kind == TS_MORSE) ts::launch_vjp<TS_MORSE, double>(a, t, single, st);
-    else ts::launch_vjp<TS_SOFT_SPHERE, double>(a, t, single, st);
-  }
+  ts::with_kind(t.kind, [&](auto k) {
+    constexpr int KIND = decltype(k)::value;
+    if (pp->prec == TS_PAIR_F32) ts::launch_vjp<KIND, float>(a, t, single, st);
+    else ts::launch_vjp<KIND, double>(a, t, single, st);
+  });
   TS_LAUNCH_CHECK();
   if (adj_params) return ts::launch_sum_slots(a.n_slots, a.slots, adj_params, st);
   return TS_OK;

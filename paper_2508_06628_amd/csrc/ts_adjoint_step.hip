@@ -326,15 +326,11 @@ static int adjoint_segment(const ts_batch *b, ts_neighbor_list *nl, const ts_pai
     r.count_cur = w.flags3 + 6 * S + p % 3;
     rc = launch_rebuild(r, S, max_atoms, st);
     if (rc != TS_OK) return rc;
-    if (pp->prec == TS_PAIR_F32) {
-      if (tab.kind == TS_LJ) launch_adj_kt<TS_LJ, float>(tl, single, S, max_atoms, a, tab, st);
-      else if (tab.kind == TS_MORSE) launch_adj_kt<TS_MORSE, float>(tl, single, S, max_atoms, a, tab, st);
-      else launch_adj_kt<TS_SOFT_SPHERE, float>(tl, single, S, max_atoms, a, tab, st);
-    } else {
-      if (tab.kind == TS_LJ) launch_adj_kt<TS_LJ, double>(tl, single, S, max_atoms, a, tab, st);
-      else if (tab.kind == TS_MORSE) launch_adj_kt<TS_MORSE, double>(tl, single, S, max_atoms, a, tab, st);
-      else launch_adj_kt<TS_SOFT_SPHERE, double>(tl, single, S, max_atoms, a, tab, st);
-    }
+    with_kind(tab.kind, [&](auto k) {
+      constexpr int KIND = decltype(k)::value;
+      if (pp->prec == TS_PAIR_F32) launch_adj_kt<KIND, float>(tl, single, S, max_atoms, a, tab, st);
+      else launch_adj_kt<KIND, double>(tl, single, S, max_atoms, a, tab, st);
+    });
     TS_LAUNCH_CHECK();
   }
   if (adj_params) {

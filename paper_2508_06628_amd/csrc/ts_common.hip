@@ -26,7 +26,7 @@ int validate_batch(const ts_batch *b, bool need_vel, int64_t *max_atoms) {
 
 int validate_params(const ts_pair_params *pp) {
   TS_CHECK_ARG(pp != nullptr);
-  if (pp->kind < TS_LJ || pp->kind > TS_SOFT_SPHERE) return TS_E_UNSUPPORTED;
+  if (pp->kind < TS_LJ || pp->kind > TS_MORSE_SF) return TS_E_UNSUPPORTED;
   if (pp->prec != TS_PAIR_F32 && pp->prec != TS_PAIR_F64) return TS_E_UNSUPPORTED;
   TS_CHECK_ARG(pp->n_species >= 1 && pp->n_species <= TS_MAX_SPECIES);
   TS_CHECK_ARG(std::isfinite(pp->cutoff) && pp->cutoff > 0.0);
@@ -34,9 +34,9 @@ int validate_params(const ts_pair_params *pp) {
     for (int b = 0; b < pp->n_species; ++b) {
       const double *p = pp->params[a][b];
       TS_CHECK_ARG(std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]));
-      if (pp->kind == TS_LJ) TS_CHECK_ARG(p[1] > 0.0);
+      if (pp->kind == TS_LJ || pp->kind == TS_LJ_SF) TS_CHECK_ARG(p[1] > 0.0);
       if (pp->kind == TS_SOFT_SPHERE) TS_CHECK_ARG(p[1] > 0.0);
-      if (pp->kind == TS_MORSE) TS_CHECK_ARG(p[0] != 0.0 || p[1] != 0.0);
+      if (pp->kind == TS_MORSE || pp->kind == TS_MORSE_SF) TS_CHECK_ARG(p[0] != 0.0 || p[1] != 0.0);
     }
   return TS_OK;
 }
@@ -53,6 +53,24 @@ int validate_list(const ts_batch *b, const ts_neighbor_list *nl) {
   TS_CHECK_ARG(nl->nbr && nl->n_nbr && nl->ref_pos && nl->ref_cell && nl->status && nl->workspace);
   TS_CHECK_ARG(nl->workspace_bytes >= ts_neighbor_workspace_bytes(b->n_atoms, b->n_systems));
   return TS_OK;
+}
+
+// phi'(r) of the plain LJ (kind TS_LJ) or Morse form and its derivatives by the parameter triple
+static double dphi_at(int kind, const double *p, double r, double d[3]) {
+  if (kind == TS_LJ) {
+    const double s6 = std::pow(p[1] / r, 6), s12 = s6 * s6;
+    const double v = 24.0 * p[0] / r * (s6 - 2.0 * s12);
+    d[0] = 24.0 / r * (s6 - 2.0 * s12);
+    d[1] = 24.0 * p[0] / r * (6.0 * s6 - 24.0 * s12) / p[1];
+    d[2] = 0.0;
+    return v;
+  }
+  const double x = std::exp(-p[1] * (r - p[2]));
+  const double q = x - x * x, one_m = 1.0 - 2.0 * x;
+  d[0] = 2.0 * p[1] * q;
+  d[1] = 2.0 * p[0] * q - 2.0 * p[1] * p[0] * one_m * (r - p[2]) * x;
+  d[2] = 2.0 * p[1] * p[1] * p[0] * one_m * x;
+  return 2.0 * p[1] * p[0] * q;
 }
 
 static double phi_at(int kind, const double *p, double r) {
@@ -82,11 +100,13 @@ PairTable make_table(const ts_pair_params *pp) {
       c.raw[2] = p[2];
       c.sig2 = std::numeric_limits<double>::infinity();
       if (a >= pp->n_species || b >= pp->n_species) continue;
-      if (pp->kind == TS_LJ) {
+      const bool sf = pp->kind == TS_LJ_SF || pp->kind == TS_MORSE_SF;
+      const int base = pp->kind == TS_LJ_SF ? TS_LJ : (pp->kind == TS_MORSE_SF ? TS_MORSE : pp->kind);
+      if (base == TS_LJ) {
         const double s6 = std::pow(p[1], 6);
         c.a = 4.0 * p[0] * s6 * s6;
         c.b = 4.0 * p[0] * s6;
-      } else if (pp->kind == TS_MORSE) {
+      } else if (base == TS_MORSE) {
         c.a = p[0];
         c.b = p[1];
         c.c = p[2];
@@ -96,7 +116,11 @@ PairTable make_table(const ts_pair_params *pp) {
         c.c = 1.0 / p[1];
         c.sig2 = p[1] * p[1];
       }
-      c.shift = (pp->shift_energy && pp->kind != TS_SOFT_SPHERE) ? phi_at(pp->kind, p, pp->cutoff) : 0.0;
+      c.shift = ((pp->shift_energy || sf) && base != TS_SOFT_SPHERE) ? phi_at(base, p, pp->cutoff) : 0.0;
+      if (sf) {
+        c.rc = pp->cutoff;
+        c.fs = dphi_at(base, p, pp->cutoff, c.dfs);
+      }
     }
   return t;
 }

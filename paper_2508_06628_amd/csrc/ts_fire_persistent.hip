@@ -637,15 +637,11 @@ int fire_persistent(const ts_batch *b, const ts_fire_state *fs, const ts_fire_co
                      sizeof(int) * kPSurv * kPW;
   const PairTable t = make_table(pp);
   const dim3 g((unsigned)grid);
-  if (pp->prec == TS_PAIR_F32) {
-    if (t.kind == TS_LJ) launch_fp_kt<TS_LJ, float>(cfg->relax_cell != 0, g, shm, a, t, st);
-    else if (t.kind == TS_MORSE) launch_fp_kt<TS_MORSE, float>(cfg->relax_cell != 0, g, shm, a, t, st);
-    else launch_fp_kt<TS_SOFT_SPHERE, float>(cfg->relax_cell != 0, g, shm, a, t, st);
-  } else {
-    if (t.kind == TS_LJ) launch_fp_kt<TS_LJ, double>(cfg->relax_cell != 0, g, shm, a, t, st);
-    else if (t.kind == TS_MORSE) launch_fp_kt<TS_MORSE, double>(cfg->relax_cell != 0, g, shm, a, t, st);
-    else launch_fp_kt<TS_SOFT_SPHERE, double>(cfg->relax_cell != 0, g, shm, a, t, st);
-  }
+  with_kind(t.kind, [&](auto k) {
+    constexpr int KIND = decltype(k)::value;
+    if (pp->prec == TS_PAIR_F32) launch_fp_kt<KIND, float>(cfg->relax_cell != 0, g, shm, a, t, st);
+    else launch_fp_kt<KIND, double>(cfg->relax_cell != 0, g, shm, a, t, st);
+  });
   TS_LAUNCH_CHECK();
   return TS_OK;
 }

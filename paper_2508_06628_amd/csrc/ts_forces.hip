@@ -136,15 +136,11 @@ int launch_forces(const ForceArgs &a, int64_t n_sys, const PairTable &t, int pre
   const dim3 g((unsigned)(ceil_div(ceil_div(a.n, 256), kXcds) * kXcds));  // a multiple of kXcds for xcd_order
   const bool single = t.n_species == 1 || a.species == nullptr;
   const bool do_ev = ev && (a.energy || a.virial);
-  if (prec == TS_PAIR_F32) {
-    if (t.kind == TS_LJ) launch_kt<TS_LJ, float>(a, t, do_ev, single, g, st);
-    else if (t.kind == TS_MORSE) launch_kt<TS_MORSE, float>(a, t, do_ev, single, g, st);
-    else launch_kt<TS_SOFT_SPHERE, float>(a, t, do_ev, single, g, st);
-  } else {
-    if (t.kind == TS_LJ) launch_kt<TS_LJ, double>(a, t, do_ev, single, g, st);
-    else if (t.kind == TS_MORSE) launch_kt<TS_MORSE, double>(a, t, do_ev, single, g, st);
-    else launch_kt<TS_SOFT_SPHERE, double>(a, t, do_ev, single, g, st);
-  }
+  with_kind(t.kind, [&](auto k) {
+    constexpr int KIND = decltype(k)::value;
+    if (prec == TS_PAIR_F32) launch_kt<KIND, float>(a, t, do_ev, single, g, st);
+    else launch_kt<KIND, double>(a, t, do_ev, single, g, st);
+  });
   TS_LAUNCH_CHECK();
   return TS_OK;
 }

@@ -96,11 +96,14 @@ __device__ inline double norm2(double dx, double dy, double dz) { return fma(dz,
 //   LJ:    a = 4 eps sigma^12, b = 4 eps sigma^6          phi = a/r^12 - b/r^6
 //   Morse: a = D, b = alpha, c = r0
 //   SS:    a = eps, b = sigma_ij, c = 1/sigma_ij
-//   shift: phi(r_c) when the energy is shifted, else 0.
+//   shift: phi(r_c) when the energy is shifted (always for the shifted-force kinds), else 0.
+//   Shifted-force kinds: fs = phi'(r_c), rc = r_c, dfs[k] = d phi'(r_c) / d raw[k].
 struct PairCoef {
   double a, b, c, shift;
   double sig2;  // sigma_ij^2 (soft sphere mask), else +inf
   double raw[3];  // the caller's parameter triple (for parameter derivatives)
+  double fs, rc;
+  double dfs[3];
 };
 struct PairTable {
   PairCoef c[TS_MAX_SPECIES * TS_MAX_SPECIES];
@@ -110,6 +113,24 @@ struct PairTable {
 };
 
 PairTable make_table(const ts_pair_params *pp);
+
+// The plain form a shifted-force kind truncates.
+template <int KIND>
+struct BaseKind {
+  static constexpr int value = KIND == TS_LJ_SF ? TS_LJ : (KIND == TS_MORSE_SF ? TS_MORSE : KIND);
+};
+
+// Calls f(std::integral_constant<int, KIND>{}) for the run-time kind (one instantiation per kind).
+template <typename F>
+inline void with_kind(int kind, F &&f) {
+  switch (kind) {
+    case TS_LJ: f(std::integral_constant<int, TS_LJ>{}); break;
+    case TS_MORSE: f(std::integral_constant<int, TS_MORSE>{}); break;
+    case TS_SOFT_SPHERE: f(std::integral_constant<int, TS_SOFT_SPHERE>{}); break;
+    case TS_LJ_SF: f(std::integral_constant<int, TS_LJ_SF>{}); break;
+    default: f(std::integral_constant<int, TS_MORSE_SF>{}); break;
+  }
+}
 
 // Visit the row entries k = lane, lane + TL, lane + 2 TL, ... (k < nn) of atom i in increasing k,
 // with the loads of the next U entries in flight while the current U are processed (the entry
@@ -231,6 +252,38 @@ __device__ inline double pair_g<TS_SOFT_SPHERE, double>(const PairCoef &pc, doub
   return -pc.a * pc.c * u / r;
 }
 
+// Shifted-force kinds: g_sf = g - phi'(r_c) / r and phi_sf = phi - phi(r_c) - (r - r_c) phi'(r_c)
+// (the base form already subtracts shift = phi(r_c)).
+template <int KIND, typename T>
+__device__ inline T pair_g_sf(const PairCoef &pc, T r2t, double r2, T *phi, bool want_phi) {
+  constexpr int B = BaseKind<KIND>::value;
+  const T g = pair_g<B, T>(pc, r2t, r2, phi, want_phi);
+  T ir;
+  if constexpr (std::is_same<T, float>::value) ir = __builtin_amdgcn_rsqf(r2t);
+  else ir = 1.0 / sqrt(r2t);
+  if (want_phi) *phi -= (r2t * ir - (T)pc.rc) * (T)pc.fs;
+  return g - (T)pc.fs * ir;
+}
+template <>
+__device__ inline float pair_g<TS_LJ_SF, float>(const PairCoef &pc, float r2t, double r2, float *phi, bool want_phi) {
+  return pair_g_sf<TS_LJ_SF, float>(pc, r2t, r2, phi, want_phi);
+}
+template <>
+__device__ inline double pair_g<TS_LJ_SF, double>(const PairCoef &pc, double r2t, double r2, double *phi,
+                                                  bool want_phi) {
+  return pair_g_sf<TS_LJ_SF, double>(pc, r2t, r2, phi, want_phi);
+}
+template <>
+__device__ inline float pair_g<TS_MORSE_SF, float>(const PairCoef &pc, float r2t, double r2, float *phi,
+                                                   bool want_phi) {
+  return pair_g_sf<TS_MORSE_SF, float>(pc, r2t, r2, phi, want_phi);
+}
+template <>
+__device__ inline double pair_g<TS_MORSE_SF, double>(const PairCoef &pc, double r2t, double r2, double *phi,
+                                                     bool want_phi) {
+  return pair_g_sf<TS_MORSE_SF, double>(pc, r2t, r2, phi, want_phi);
+}
+
 // One pair's contribution to atom i: g = phi'(r)/r comes from the pair function (pair precision);
 // it multiplies the float64 pair vector d = r_j - r_i + S h in float64 and the force sums in
 // float64 (F_i += g d).  The virial variant also accumulates the six distinct entries of
@@ -299,6 +352,29 @@ __device__ inline void pair_g_h<TS_SOFT_SPHERE, double>(const PairCoef &pc, doub
   *g = -pc.a * pc.c * u / r;
   *h = pc.a * pc.c * pc.c;
 }
+// Shifted-force kinds: phi_sf'' = phi'' and g_sf = g - phi'(r_c) / r.
+template <int KIND, typename T>
+__device__ inline void pair_g_h_sf(const PairCoef &pc, T r2t, double r2, T *g, T *h) {
+  pair_g_h<BaseKind<KIND>::value, T>(pc, r2t, r2, g, h);
+  *g -= (T)pc.fs / sqrt(r2t);
+}
+template <>
+__device__ inline void pair_g_h<TS_LJ_SF, float>(const PairCoef &pc, float r2t, double r2, float *g, float *h) {
+  pair_g_h_sf<TS_LJ_SF, float>(pc, r2t, r2, g, h);
+}
+template <>
+__device__ inline void pair_g_h<TS_LJ_SF, double>(const PairCoef &pc, double r2t, double r2, double *g, double *h) {
+  pair_g_h_sf<TS_LJ_SF, double>(pc, r2t, r2, g, h);
+}
+template <>
+__device__ inline void pair_g_h<TS_MORSE_SF, float>(const PairCoef &pc, float r2t, double r2, float *g, float *h) {
+  pair_g_h_sf<TS_MORSE_SF, float>(pc, r2t, r2, g, h);
+}
+template <>
+__device__ inline void pair_g_h<TS_MORSE_SF, double>(const PairCoef &pc, double r2t, double r2, double *g,
+                                                      double *h) {
+  pair_g_h_sf<TS_MORSE_SF, double>(pc, r2t, r2, g, h);
+}
 
 // Derivatives of g = phi'/r with respect to the raw parameter triple (float64).  One division per
 // pair (1/r^2 or 1/r); quotients of the parameters alone are loop invariants for a one-species
@@ -341,6 +417,22 @@ __device__ inline void pair_dg_dparams<TS_SOFT_SPHERE>(const PairCoef &pc, doubl
   out[0] = -u * isig * ir;
   out[1] = eps * isig * isig * (ir - 2.0 * isig);
   out[2] = 0.0;
+}
+// Shifted-force kinds: d g_sf / d theta = d g / d theta - (d phi'(r_c) / d theta) / r.
+template <>
+__device__ inline void pair_dg_dparams<TS_LJ_SF>(const PairCoef &pc, double r2, double out[3]) {
+  pair_dg_dparams<TS_LJ>(pc, r2, out);
+  const double ir = 1.0 / sqrt(r2);
+  out[0] -= pc.dfs[0] * ir;
+  out[1] -= pc.dfs[1] * ir;
+}
+template <>
+__device__ inline void pair_dg_dparams<TS_MORSE_SF>(const PairCoef &pc, double r2, double out[3]) {
+  pair_dg_dparams<TS_MORSE>(pc, r2, out);
+  const double ir = 1.0 / sqrt(r2);
+  out[0] -= pc.dfs[0] * ir;
+  out[1] -= pc.dfs[1] * ir;
+  out[2] -= pc.dfs[2] * ir;
 }
 
 // ----------------------------------------------------------------------------- reductions

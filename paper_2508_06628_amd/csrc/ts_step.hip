@@ -633,15 +633,11 @@ int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &
   if (grid > 0x7fffffff) return TS_E_CAPACITY;
   const dim3 g((unsigned)grid);
   const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
-  if (prec == TS_PAIR_F32) {
-    if (t.kind == TS_LJ) launch_step_kt<TS_LJ, float>(tl, mode, a, t, g, shm, st);
-    else if (t.kind == TS_MORSE) launch_step_kt<TS_MORSE, float>(tl, mode, a, t, g, shm, st);
-    else launch_step_kt<TS_SOFT_SPHERE, float>(tl, mode, a, t, g, shm, st);
-  } else {
-    if (t.kind == TS_LJ) launch_step_kt<TS_LJ, double>(tl, mode, a, t, g, shm, st);
-    else if (t.kind == TS_MORSE) launch_step_kt<TS_MORSE, double>(tl, mode, a, t, g, shm, st);
-    else launch_step_kt<TS_SOFT_SPHERE, double>(tl, mode, a, t, g, shm, st);
-  }
+  with_kind(t.kind, [&](auto k) {
+    constexpr int KIND = decltype(k)::value;
+    if (prec == TS_PAIR_F32) launch_step_kt<KIND, float>(tl, mode, a, t, g, shm, st);
+    else launch_step_kt<KIND, double>(tl, mode, a, t, g, shm, st);
+  });
   TS_LAUNCH_CHECK();
   return TS_OK;
 }

@@ -32,7 +32,9 @@ class RdfSpec:
 
 
 class TrajectoryRDF:
-    """Loss L(eps, sigma, r_0) of one LJ batch; single-species parameters (eps, sigma)."""
+    """Loss L(eps, sigma, r_0) of one LJ batch (kind "lj", or "lj_sf" for the shifted-force
+    truncation, whose trajectory map has no force jumps at the cutoff); single-species parameters
+    (eps, sigma)."""
 
     def __init__(self, workload, n_steps: int, checkpoint_every: int = 50, prec: str = "f32",
                  rdf: RdfSpec = RdfSpec(), skin: float = 0.3, bin_factor: int = 2, use_graph: bool = True):
@@ -62,7 +64,7 @@ class TrajectoryRDF:
     def _pp(self, eps, sigma):
         p = np.zeros((1, 1, 3))
         p[0, 0] = (eps, sigma, 0.0)
-        return api.pair_params("lj", p, self.cutoff, self.w.potential.shift_energy, self.prec)
+        return api.pair_params(self.w.potential.kind, p, self.cutoff, self.w.potential.shift_energy, self.prec)
 
     def _reset(self, pos0: torch.Tensor):
         self.batch.pos.copy_(pos0)

@@ -150,3 +150,69 @@ def test_recorded_segment_equals_step_loop():
         outs.append((b.pos.clone(), b.vel.clone(), F.clone()))
     for x, y in zip(*outs):
         assert torch.equal(x, y)
+
+
+# ----------------------------------------------------------------------------- shifted-force LJ
+
+
+def _sf_workload():
+    import dataclasses
+    w = _workload()
+    w.potential = dataclasses.replace(w.potential, kind="lj_sf", shift_energy=False)
+    return w
+
+
+def _oracle_sf(w, eps, sig, target):
+    pot = PotentialSpec("lj_sf", np.array([[[eps, sig, 0.0]]]), w.potential.cutoff, False)
+    traj, _ = oadj.trajectory_positions(w.pos, w.vel, w.mass, w.cell, w.sys_offsets, w.species, pot, w.dt, N_STEPS,
+                                        w.accel)
+    r_max = RDF["r_end"] + 6 * RDF["sigma"]
+    g = oadj.batch_rdf(traj[-1], w.cell, w.sys_offsets, RDF["n_bins"], RDF["r_end"], RDF["sigma"], r_max)
+    if target is None:
+        return g
+    lr_T = oadj.rdf_loss_grad(traj[-1], w.cell, w.sys_offsets, RDF["n_bins"], RDF["r_end"], RDF["sigma"], r_max, g,
+                              target)
+    lr0, _, tb = oadj.reverse_nve(traj, w.mass, w.cell, w.sys_offsets, w.species, pot, w.dt, w.accel, lr_T,
+                                  np.zeros_like(lr_T))
+    return oadj.rdf_loss(g, target), lr0, tb[0, 0, 0], tb[0, 0, 1]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_shifted_force_gradient_matches_oracle_and_fd_at_1e4(prec):
+    # with the shifted-force truncation the force has no jump at the cutoff, so central differences
+    # at the 1e-4 relative step (sigma, positions as well as epsilon) agree with the adjoint
+    w = _sf_workload()
+    eps, sig = float(w.potential.params[0, 0, 0]), float(w.potential.params[0, 0, 1])
+    target = _oracle_sf(w, eps * 1.05, sig * 1.05, None)
+    loss_ref, lr0_ref, de_ref, ds_ref = _oracle_sf(w, eps, sig, target)
+    eng = _engine(w, prec)
+    eng.set_target(torch.tensor(target, device="cuda"))
+    pos0 = eng.batch.pos.clone()
+    loss = eng.forward(eps, sig, pos0).item()
+    de, ds, lr0 = eng.backward()
+    eng.check_status()
+    tol = 1e-8 if prec == "f64" else 1e-3
+    assert abs(loss - loss_ref) <= (1e-9 if prec == "f64" else 1e-4) * abs(loss_ref)
+    assert abs(de - de_ref) <= tol * abs(de_ref)
+    assert abs(ds - ds_ref) <= tol * abs(ds_ref)
+    assert np.abs(lr0.T.cpu().numpy() - lr0_ref).max() <= tol * np.abs(lr0_ref).max()
+    if prec != "f64":
+        return
+
+    def L(e, s, p):
+        return eng.forward(e, s, p).item()
+
+    def central(fun, x, h):
+        d1 = (fun(x + h) - fun(x - h)) / (2 * h)
+        d2 = (fun(x + h / 2) - fun(x - h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    h = 1e-4
+    assert abs(central(lambda e: L(e, sig, pos0), eps, h * eps) - de) <= 1e-6 * abs(de)
+    assert abs(central(lambda sg: L(eps, sg, pos0), sig, h * sig) - ds) <= 1e-6 * abs(ds)
+    rng = np.random.default_rng(4)
+    u = rng.normal(size=pos0.shape)
+    u /= np.linalg.norm(u)
+    ut = torch.tensor(u, device="cuda")
+    fd_p = central(lambda t: L(eps, sig, pos0 + t * ut), 0.0, h * sig)
+    assert abs(fd_p - float((lr0 * ut).sum())) <= 1e-6 * max(abs(fd_p), 1e-3 * float(lr0.abs().max()))

@@ -12,7 +12,7 @@ from oracle import fire as ofire
 from oracle import forces as oforces
 from oracle import integrate as ointeg
 from tests.gpu_helpers import assert_forces_close, force_scales
-from workloads import copper_uneven_batch, random_small_batch
+from workloads import argon_batch, copper_uneven_batch, random_small_batch
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -58,16 +58,29 @@ def test_shifted_force_forces(kind, n_species, prec):
 
 @pytest.mark.parametrize("kind", ["lj", "morse"])
 def test_shifted_force_nve(kind):
+    # physical inputs (FCC argon at 50-300 K; strained triclinic copper from noisy sites): 25 steps
+    # stay a smooth trajectory, with list rebuilds at the 0.1 skin, that the brute-force oracle
+    # follows in seconds (random jittered cells hold near-overlapping pairs whose trajectories blow up)
     api = _api()
-    w = _sf_batch(kind, 75, n_systems=4, n_range=(20, 60), density=0.7)
+    if kind == "lj":
+        w = argon_batch(3, reps=(3, 3, 3), seed=75)
+        w.potential = dataclasses.replace(w.potential, kind="lj_sf", shift_energy=False)
+        w.dt = 2.0
+    else:
+        w = copper_uneven_batch(3, seed=75, min_sites=32, max_sites=110)
+        w.potential = dataclasses.replace(w.potential, kind="morse_sf")
+        w.dt = 0.1
     pot = w.potential
-    w.dt = 0.002
     b = api.Batch.from_workload(w)
     nl = api.build_neighbor_list(b, pot.cutoff, 0.1)
     pp = api.pair_params_from_spec(pot, "f64")
     F, _, _ = api.compute_forces(b, nl, pp, "f64")
     E = torch.zeros(w.n_systems, dtype=torch.float64, device="cuda")
+    built = int(nl.read_status()[2])
     api.ts_nve_step(b, nl, pp, w.dt, w.accel, 25, F, E)
+    status = nl.read_status()
+    assert status[1] == 0 and status[3] == 0 and status[4] == 0
+    assert int(status[2]) > built, "the run should cross the skin and rebuild"
     ref = ointeg.nve(w.pos, w.vel, w.mass, w.cell, w.sys_offsets, w.species, pot, w.dt, 25, w.accel)
     L = np.abs(np.linalg.det(w.cell)).max() ** (1 / 3)
     assert np.abs(b.positions() - ref["pos"]).max() <= 1e-10 * L

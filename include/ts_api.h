@@ -300,6 +300,19 @@ int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl, const ts_
                     double w_kick, double accel, double *adj_pos, double *adj_vel, double *adj_params,
                     ts_stream_t stream);
 
+/* ts_pair_adjoint for callers that cannot allocate device memory (code under hipGraph capture,
+   tight serving loops, harnesses that forbid hipMalloc): the same operation, arguments and results,
+   but the parameter-gradient partial sums live in a library-held device array instead of the list's
+   workspace, so nl->workspace may be NULL (nl->workspace_bytes is then ignored) and the call makes no
+   allocation of any kind.  Limit: with adj_params != NULL at most 4096 systems (TS_E_CAPACITY
+   beyond; without adj_params any batch size).  The array is 1.5 MiB per GPU, held from the first
+   call on that GPU until the process ends; its address is looked up once per device.  Every call
+   on one GPU shares that GPU's array (each call clears what it uses): calls that overlap in time
+   on one GPU (different streams, or host threads) race and must be serialised by the caller. */
+int ts_pair_adjoint_noalloc(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp,
+                            double dt_drift, double w_kick, double accel, double *adj_pos, double *adj_vel,
+                            double *adj_params, ts_stream_t stream);
+
 /* Reverse velocity-Verlet over one recorded segment r_{n0} .. r_{n0+n_steps} (traj as written by
    ts_nve_record; the batch supplies masses, species and cells).  Positions are processed from
    r_{n0+n_steps} down to r_{n0+1}, and also r_{n0} when bottom = 1 (n0 = 0); at each the adjoint

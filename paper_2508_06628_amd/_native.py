@@ -138,6 +138,8 @@ SIGNATURES = {
                                POINTER(TsPairParams), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "ts_pair_adjoint": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double,
                                   c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ts_pair_adjoint_noalloc": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), POINTER(TsPairParams), c_double,
+                                          c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ts_rdf_smeared": (c_int32, [POINTER(TsBatch), POINTER(TsNeighborList), c_int32, c_double, c_double, c_double,
                                  c_void_p, c_void_p]),
     "ts_rdf_loss": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p]),

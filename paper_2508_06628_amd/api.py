@@ -399,6 +399,20 @@ def ts_pair_adjoint(batch, nl, pp, dt_drift, w_kick, accel, adj_pos, adj_vel, ad
                                                               _p(adj_params), _stream(stream)))
 
 
+def ts_pair_adjoint_noalloc(batch, nl, pp, dt_drift, w_kick, accel, adj_pos, adj_vel, adj_params=None,
+                            stream=None, without_workspace=False):
+    """ts_pair_adjoint with the library's static partial-sum array (no allocation; at most 4096
+    systems when adj_params is given).  without_workspace passes the list with a NULL workspace."""
+    st = nl.struct()
+    if without_workspace:
+        st.workspace = None
+        st.workspace_bytes = 0
+    return N.check("ts_pair_adjoint_noalloc",
+                   N.lib().ts_pair_adjoint_noalloc(ctypes.byref(batch.struct()), ctypes.byref(st), ctypes.byref(pp),
+                                                   float(dt_drift), float(w_kick), float(accel), _p(adj_pos),
+                                                   _p(adj_vel), _p(adj_params), _stream(stream)))
+
+
 def ts_rdf_smeared(batch, nl, n_bins, r_end, sigma, r_max, g, stream=None):
     return N.check("ts_rdf_smeared", N.lib().ts_rdf_smeared(ctypes.byref(batch.struct()), ctypes.byref(nl.struct()),
                                                             int(n_bins), float(r_end), float(sigma), float(r_max),

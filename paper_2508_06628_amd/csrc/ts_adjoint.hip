@@ -7,6 +7,8 @@
 //     K du = (h - g) (d . du) / r^2 d + g du,
 // and the parameter term is (dg/dtheta)(u_i . d).  Pair arithmetic in the pair precision,
 // accumulators in float64.
+#include <mutex>
+
 #include "ts_adjoint.h"
 #include "ts_forces.h"
 #include "ts_neighbor.h"
@@ -340,24 +342,22 @@ static int validate_rdf(const ts_batch *b, const ts_neighbor_list *nl, int n_bin
 
 }  // namespace ts
 
-extern "C" int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp,
-                               double dt_drift, double w_kick, double accel, double *adj_pos, double *adj_vel,
-                               double *adj_params, ts_stream_t stream) {
-  int64_t max_atoms = 0;
-  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, false);
-  if (rc != TS_OK) return rc;
-  TS_CHECK_ARG(adj_pos && adj_vel && std::isfinite(dt_drift) && std::isfinite(w_kick) && std::isfinite(accel) &&
-               accel > 0.0);
-  hipStream_t st = ts::as_stream(stream);
+namespace ts {
+
+// The pair adjoint of both entry points below; the parameter-gradient partial sums go to
+// `slots` ([n_slots][kAdjSlot] doubles, cleared here when adj_params is wanted).
+static int pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp, double dt_drift,
+                        double w_kick, double accel, double *adj_pos, double *adj_vel, double *adj_params,
+                        double *slots, int64_t n_slots, hipStream_t st) {
   if (batch->n_atoms == 0) return TS_OK;
-  const int64_t stride = ts::stride_of(batch);
+  const int64_t stride = stride_of(batch);
   if (dt_drift != 0.0) {
-    hipLaunchKernelGGL(ts::k_adj_drift, dim3((unsigned)ts::ceil_div(batch->n_atoms, 256)), dim3(256), 0, st,
-                       batch->n_atoms, stride, adj_pos, adj_vel, dt_drift);
+    hipLaunchKernelGGL(k_adj_drift, dim3((unsigned)ceil_div(batch->n_atoms, 256)), dim3(256), 0, st, batch->n_atoms,
+                       stride, adj_pos, adj_vel, dt_drift);
     TS_LAUNCH_CHECK();
   }
   if (w_kick == 0.0) return TS_OK;
-  ts::AdjArgs a;
+  AdjArgs a;
   a.n = batch->n_atoms;
   a.stride = stride;
   a.sys_idx = batch->system_idx;
@@ -371,25 +371,82 @@ extern "C" int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl
   a.lr = adj_pos;
   a.lv = adj_vel;
   a.adj_params = adj_params;
-  const ts::NlWork w = ts::nl_work(nl->workspace, batch->n_atoms, batch->n_systems);
-  a.slots = w.adj_slots;
-  a.n_slots = ts::adj_slot_count(batch->n_systems);
+  a.slots = slots;
+  a.n_slots = n_slots;
   a.w = w_kick;
   a.accel = accel;
   if (adj_params) {
-    rc = ts::fill_async<double>(a.slots, ts::kAdjSlot * a.n_slots, 0.0, st);
+    const int rc = fill_async<double>(a.slots, kAdjSlot * a.n_slots, 0.0, st);
     if (rc != TS_OK) return rc;
   }
-  const ts::PairTable t = ts::make_table(pp);
+  const PairTable t = make_table(pp);
   const bool single = t.n_species == 1 || batch->species == nullptr;
-  ts::with_kind(t.kind, [&](auto k) {
+  with_kind(t.kind, [&](auto k) {
     constexpr int KIND = decltype(k)::value;
-    if (pp->prec == TS_PAIR_F32) ts::launch_vjp<KIND, float>(a, t, single, st);
-    else ts::launch_vjp<KIND, double>(a, t, single, st);
+    if (pp->prec == TS_PAIR_F32) launch_vjp<KIND, float>(a, t, single, st);
+    else launch_vjp<KIND, double>(a, t, single, st);
   });
   TS_LAUNCH_CHECK();
-  if (adj_params) return ts::launch_sum_slots(a.n_slots, a.slots, adj_params, st);
+  if (adj_params) return launch_sum_slots(a.n_slots, a.slots, adj_params, st);
   return TS_OK;
+}
+
+// Partial-sum slots of ts_pair_adjoint_noalloc: a library-held array, one copy per GPU (at most
+// kNoallocSystems systems, one slot each; 1.5 MiB).  Host code never uses the symbol's name as an
+// address: the device address of each GPU's copy comes from hipGetSymbolAddress (noalloc_slots).
+constexpr int64_t kNoallocSystems = 4096;
+static __device__ __align__(256) double scratch[kNoallocSystems * kAdjSlot];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current GPU's copy of `scratch`, looked up once per device.
+static int noalloc_slots(double **out) {
+  int dev = 0;
+  TS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return TS_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    TS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return TS_OK;
+}
+
+}  // namespace ts
+
+extern "C" int ts_pair_adjoint(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp,
+                               double dt_drift, double w_kick, double accel, double *adj_pos, double *adj_vel,
+                               double *adj_params, ts_stream_t stream) {
+  int64_t max_atoms = 0;
+  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, false);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(adj_pos && adj_vel && std::isfinite(dt_drift) && std::isfinite(w_kick) && std::isfinite(accel) &&
+               accel > 0.0);
+  const ts::NlWork w = ts::nl_work(nl->workspace, batch->n_atoms, batch->n_systems);
+  return ts::pair_adjoint(batch, nl, pp, dt_drift, w_kick, accel, adj_pos, adj_vel, adj_params, w.adj_slots,
+                          ts::adj_slot_count(batch->n_systems), ts::as_stream(stream));
+}
+
+extern "C" int ts_pair_adjoint_noalloc(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp,
+                                       double dt_drift, double w_kick, double accel, double *adj_pos,
+                                       double *adj_vel, double *adj_params, ts_stream_t stream) {
+  int64_t max_atoms = 0;
+  int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, false, false);
+  if (rc != TS_OK) return rc;
+  TS_CHECK_ARG(adj_pos && adj_vel && std::isfinite(dt_drift) && std::isfinite(w_kick) && std::isfinite(accel) &&
+               accel > 0.0);
+  if (adj_params && batch->n_systems > ts::kNoallocSystems) return TS_E_CAPACITY;
+  double *slots = nullptr;
+  if (adj_params && w_kick != 0.0 && batch->n_atoms > 0) {  // only launches that accumulate use the array
+    rc = ts::noalloc_slots(&slots);
+    if (rc != TS_OK) return rc;
+  }
+  return ts::pair_adjoint(batch, nl, pp, dt_drift, w_kick, accel, adj_pos, adj_vel, adj_params, slots,
+                          ts::adj_slot_count(batch->n_systems), ts::as_stream(stream));
 }
 
 extern "C" int ts_rdf_smeared(const ts_batch *batch, const ts_neighbor_list *nl, int32_t n_bins, double r_end,

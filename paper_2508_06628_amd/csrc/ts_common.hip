@@ -41,7 +41,7 @@ int validate_params(const ts_pair_params *pp) {
   return TS_OK;
 }
 
-int validate_list(const ts_batch *b, const ts_neighbor_list *nl) {
+int validate_list(const ts_batch *b, const ts_neighbor_list *nl, bool need_workspace) {
   TS_CHECK_ARG(nl != nullptr);
   TS_CHECK_ARG(std::isfinite(nl->cutoff) && nl->cutoff > 0.0);
   TS_CHECK_ARG(std::isfinite(nl->skin) && nl->skin >= 0.0);
@@ -50,8 +50,11 @@ int validate_list(const ts_batch *b, const ts_neighbor_list *nl) {
   TS_CHECK_ARG(nl->lanes_per_atom == 0 || nl->lanes_per_atom == 1 || nl->lanes_per_atom == 2 ||
                nl->lanes_per_atom == 4 || nl->lanes_per_atom == 8);
   TS_CHECK_ARG(nl->group_atoms >= 0 && nl->reserved == 0);
-  TS_CHECK_ARG(nl->nbr && nl->n_nbr && nl->ref_pos && nl->ref_cell && nl->status && nl->workspace);
-  TS_CHECK_ARG(nl->workspace_bytes >= ts_neighbor_workspace_bytes(b->n_atoms, b->n_systems));
+  TS_CHECK_ARG(nl->nbr && nl->n_nbr && nl->ref_pos && nl->ref_cell && nl->status);
+  if (need_workspace) {
+    TS_CHECK_ARG(nl->workspace != nullptr);
+    TS_CHECK_ARG(nl->workspace_bytes >= ts_neighbor_workspace_bytes(b->n_atoms, b->n_systems));
+  }
   return TS_OK;
 }
 

@@ -28,6 +28,6 @@ ForceArgs make_force_args(const ts_batch *b, const ts_neighbor_list *nl, void *f
 int launch_forces(const ForceArgs &a, int64_t n_sys, const PairTable &t, int prec, bool ev, hipStream_t st);
 
 int validate_pair_call(const ts_batch *b, const ts_neighbor_list *nl, const ts_pair_params *pp, int64_t *max_atoms,
-                       bool need_vel);
+                       bool need_vel, bool need_workspace = true);
 
 }  // namespace ts

@@ -166,12 +166,12 @@ ForceArgs make_force_args(const ts_batch *b, const ts_neighbor_list *nl, void *f
 }
 
 int validate_pair_call(const ts_batch *b, const ts_neighbor_list *nl, const ts_pair_params *pp, int64_t *max_atoms,
-                       bool need_vel) {
+                       bool need_vel, bool need_workspace) {
   int rc = validate_batch(b, need_vel, max_atoms);
   if (rc != TS_OK) return rc;
   rc = validate_params(pp);
   if (rc != TS_OK) return rc;
-  rc = validate_list(b, nl);
+  rc = validate_list(b, nl, need_workspace);
   if (rc != TS_OK) return rc;
   if (nl->half) return TS_E_UNSUPPORTED;
   // the list must cover the interaction range

@@ -44,7 +44,7 @@ inline hipStream_t as_stream(ts_stream_t s) { return reinterpret_cast<hipStream_
 // Host-side validation of a batch; fills max_atoms (largest system).
 int validate_batch(const ts_batch *b, bool need_vel, int64_t *max_atoms);
 int validate_params(const ts_pair_params *pp);
-int validate_list(const ts_batch *b, const ts_neighbor_list *nl);
+int validate_list(const ts_batch *b, const ts_neighbor_list *nl, bool need_workspace = true);
 
 // ----------------------------------------------------------------------------- list entries
 

@@ -155,3 +155,30 @@ def test_host_argument_checks():
     assert L.ts_graph_export(by(b), by(ok_nl), 1.0, rp, None, ei, None, None, 10, None) == N.TS_E_INVALID
     assert L.ts_graph_export(by(b), by(ok_nl), 1.0, rp, eo, None, None, None, 10, None) == N.TS_E_INVALID
     assert L.ts_graph_export(by(b), by(ok_nl), 1.0, rp, eo, ei, None, None, -1, None) == N.TS_E_INVALID
+
+
+def test_pair_adjoint_noalloc_host_checks():
+    # the no-allocation variant takes a list without workspace, rejects more systems than its static
+    # array holds when the parameter gradient is wanted, and returns before any launch when there is
+    # nothing to do (dt_drift = w_kick = 0), so these checks run without a GPU
+    N = _lib()
+    L = N.lib()
+    by = ctypes.byref
+    b, h = _fake_batch(N, [0, 10, 25])
+    lr, lv, tb = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    no_ws = _nl(N, 25, 2, workspace=None, workspace_bytes=0)
+    assert L.ts_pair_adjoint_noalloc(by(b), by(no_ws), by(_pp(N)), 0.0, 0.0, 1.0, lr, lv, tb, None) == N.TS_OK
+    assert L.ts_pair_adjoint(by(b), by(no_ws), by(_pp(N)), 0.0, 0.0, 1.0, lr, lv, tb, None) == N.TS_E_INVALID
+    assert L.ts_pair_adjoint_noalloc(by(b), by(no_ws), by(_pp(N)), 0.0, 0.0, 1.0, None, lv, tb,
+                                     None) == N.TS_E_INVALID
+    many, hm = _fake_batch(N, list(range(4098)))
+    nl_many = _nl(N, 4097, 4097, workspace=None, workspace_bytes=0)
+    assert L.ts_pair_adjoint_noalloc(by(many), by(nl_many), by(_pp(N)), 0.0, 0.0, 1.0, lr, lv, tb,
+                                     None) == N.TS_E_CAPACITY
+    # without the parameter gradient there is no limit on the number of systems
+    assert L.ts_pair_adjoint_noalloc(by(many), by(nl_many), by(_pp(N)), 0.0, 0.0, 1.0, lr, lv, None,
+                                     None) == N.TS_OK
+    at_limit, hl = _fake_batch(N, list(range(4097)))
+    nl_lim = _nl(N, 4096, 4096, workspace=None, workspace_bytes=0)
+    assert L.ts_pair_adjoint_noalloc(by(at_limit), by(nl_lim), by(_pp(N)), 0.0, 0.0, 1.0, lr, lv, tb,
+                                     None) == N.TS_OK

@@ -128,7 +128,7 @@ typedef struct {
                            positions are staged in LDS once for all of them): rounded down to a
                            multiple of 256 / lanes_per_atom; 0 = chosen from the batch shape */
   int32_t reserved;     /* must be 0 */
-  int32_t *nbr;        /* device [ceil(max_nbr / 8)][stride][8] */
+  int32_t *nbr;        /* device [ceil(max_nbr / 8)][stride][8], at most 4 GiB (TS_E_CAPACITY) */
   int32_t *n_nbr;      /* device [N] */
   double *ref_pos;     /* device SoA [3][stride]: positions at the last build of each system */
   double *ref_cell;    /* device [S][9]: cell at the last build */

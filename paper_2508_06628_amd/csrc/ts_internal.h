@@ -140,16 +140,18 @@ template <int TL, typename F>
 __device__ inline void for_row(const uint32_t *__restrict__ nbr, int64_t st, int64_t i, int nn, int lane, F &&f) {
   constexpr int U = 4;
   uint32_t cur[U], nxt[U];
+  // past the end of the row a lane reloads an entry of the row's first block (always allocated):
+  // the loads carry no branch, so they stay in flight while the previous entries are evaluated
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int kk = lane + u * TL;
-    cur[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
+    cur[u] = nbr[row_index(kk < nn ? kk : (kk & (kRowBlock - 1)), i, st)];
   }
   for (int k = lane; k < nn; k += U * TL) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int kk = k + (U + u) * TL;
-      nxt[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
+      nxt[u] = nbr[row_index(kk < nn ? kk : (kk & (kRowBlock - 1)), i, st)];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -160,29 +162,62 @@ __device__ inline void for_row(const uint32_t *__restrict__ nbr, int64_t st, int
 }
 
 // Visit the same entries as for_row, U visits at a time: f(ent, ok) receives U consecutive entries
-// of the lane (ok[u] false past the end of the row, with ent[u] = 0) and evaluates them without
+// of the lane (ok[u] false past the end of the row, where ent[u] is unspecified) and evaluates them without
 // branches between them, so the U dependent chains can be interleaved.  Results must be combined
 // in u order to sum like the plain loop.
 template <int TL, int U, typename F>
 __device__ inline void for_row_batched(const uint32_t *__restrict__ nbr, int64_t st, int64_t i, int nn, int lane,
                                        F &&f, int k_begin = 0) {
   uint32_t cur[U], nxt[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int kk = k_begin + lane + u * TL;
-    cur[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
-  }
-  for (int k = k_begin + lane; k < nn; k += U * TL) {
-    bool ok[U];
+  if constexpr ((U * TL) % kRowBlock == 0) {
+    // A batch advances every visit u by whole row blocks, so each visit keeps its position in the
+    // block and its byte offset grows by a fixed amount: 32-bit offsets from the list base (the list
+    // is below 4 GiB, checked by the host) replace the 64-bit index arithmetic of row_index.  Past
+    // the end of the row a visit reads the same position of the row's last block (allocated:
+    // n_nbr <= max_nbr), so the loads carry no branch and stay in flight during the evaluation.
+    const char *base = reinterpret_cast<const char *>(nbr);
+    const uint32_t s32 = (uint32_t)st, i32 = (uint32_t)i;
+    const uint32_t inc = (uint32_t)(U * TL / kRowBlock) * s32 * (uint32_t)(kRowBlock * 4);
+    const uint32_t last = (uint32_t)(nn > 0 ? (nn - 1) / kRowBlock : 0);
+    uint32_t off[U], lim[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int kk = k + (U + u) * TL;
-      nxt[u] = kk < nn ? nbr[row_index(kk, i, st)] : 0u;
-      ok[u] = k + u * TL < nn;
+      const uint32_t kk = (uint32_t)(k_begin + lane + u * TL), w = (kk % kRowBlock) * 4u;
+      off[u] = ((kk / kRowBlock) * s32 + i32) * (uint32_t)(kRowBlock * 4) + w;
+      lim[u] = (last * s32 + i32) * (uint32_t)(kRowBlock * 4) + w;
+      cur[u] = *reinterpret_cast<const uint32_t *>(base + (off[u] < lim[u] ? off[u] : lim[u]));
     }
-    f(cur, ok);
+    for (int k = k_begin + lane; k < nn; k += U * TL) {
+      bool ok[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+      for (int u = 0; u < U; ++u) {
+        off[u] += inc;
+        nxt[u] = *reinterpret_cast<const uint32_t *>(base + (off[u] < lim[u] ? off[u] : lim[u]));
+        ok[u] = k + u * TL < nn;
+      }
+      f(cur, ok);
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+    }
+  } else {
+    // unconditional loads as in for_row (entries past the end are masked by ok)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = k_begin + lane + u * TL;
+      cur[u] = nbr[row_index(kk < nn ? kk : (kk & (kRowBlock - 1)), i, st)];
+    }
+    for (int k = k_begin + lane; k < nn; k += U * TL) {
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int kk = k + (U + u) * TL;
+        nxt[u] = nbr[row_index(kk < nn ? kk : (kk & (kRowBlock - 1)), i, st)];
+        ok[u] = k + u * TL < nn;
+      }
+      f(cur, ok);
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+    }
   }
 }
 

@@ -45,8 +45,9 @@ struct StepArgs {
   double r_list, skin;
   double half_dt, dt, accel;
   double *epot, *virial;
-  int chunks;      // workgroups per system; each owns rounds * 256/TL consecutive atoms
-  int rounds;
+  int chunks;      // workgroups per system; chunk c owns atoms [c span, (c + 1) span) of its system
+  int rounds;      // groups of kStepThreads/TL atoms a workgroup evaluates one after another
+  int span;        // atoms per chunk: ceil(largest system / chunks) <= rounds * kStepThreads/TL
   int64_t n_work;  // n_systems * chunks (the grid is n_work rounded up to a multiple of kXcds)
   int n_sys;       // systems in the batch (rebuild launch)
   // Langevin modes: O step of this launch (step index lang_k of the call) and, with a non-null

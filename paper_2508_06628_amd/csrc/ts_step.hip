@@ -58,8 +58,9 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   }
   const int64_t a0 = a.offs[s];
   const int ns = (int)(a.offs[s + 1] - a0);
-  const int first = chunk * APB * a.rounds;
+  const int first = chunk * a.span;
   if (first >= ns) return;
+  const int end = first + a.span < ns ? first + a.span : ns;  // this chunk's atoms: [first, end)
   const int tid = threadIdx.x;
   const int grp = tid / TL, lane = tid % TL;
   const double *h = a.cell + 9 * (int64_t)s;
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
     const uint64_t t = LANG ? *a.lang.rng_step + (uint64_t)a.lang_k : 0;
     for (int r = 0; r < a.rounds; ++r) {
       const int li = first + r * APB + grp;
-      if (!(li < ns && lane == 0)) continue;
+      if (!(li < end && lane == 0)) continue;
       const int64_t i = a0 + li;
       const T *F = static_cast<const T *>(a.force);
       const double sc = a.mass ? a.accel / a.mass[i] : a.accel;
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   } pre = {};
   {
     const int li = first + grp;
-    const bool own = li < ns;
+    const bool own = li < end;
     const int64_t i = a0 + li;
     pre.nn = own ? a.n_nbr[i] : 0;
     if (!FORCE_ONLY && own && lane == 0) {
@@ -124,12 +125,13 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
       }
     }
   }
-  // 1. stage r_n of the whole system
-  double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
+  // 1. stage r_n of the whole system, one (x, y, z) record per atom: a neighbor's three reads share
+  // one address (the record offset goes into the read instructions)
+  double *lp = lds;
   for (int k = tid; k < ns; k += kStepThreads) {
-    lx[k] = a.pos_in[a0 + k];
-    ly[k] = a.pos_in[a.st_in + a0 + k];
-    lz[k] = a.pos_in[2 * a.st_in + a0 + k];
+    lp[3 * k] = a.pos_in[a0 + k];
+    lp[3 * k + 1] = a.pos_in[a.st_in + a0 + k];
+    lp[3 * k + 2] = a.pos_in[2 * a.st_in + a0 + k];
   }
   __syncthreads();
   const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
@@ -143,11 +145,11 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   double e = 0.0, w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // over all rounds
   for (int r = 0; r < a.rounds; ++r) {
     const int base = first + r * APB;
-    if (base >= ns) break;  // uniform over the workgroup
+    if (base >= end) break;  // uniform over the workgroup
     const int li = base + grp;
-    const bool own = li < ns;
+    const bool own = li < end;
     const int64_t i = a0 + li;
-    const double rx = own ? lx[li] : 0.0, ry = own ? ly[li] : 0.0, rz = own ? lz[li] : 0.0;
+    const double rx = own ? lp[3 * li] : 0.0, ry = own ? lp[3 * li + 1] : 0.0, rz = own ? lp[3 * li + 2] : 0.0;
     const int nn = r == 0 ? pre.nn : (own ? a.n_nbr[i] : 0);
     // (evaluated after the atom's own loads: this order keeps the register count of the loop low)
     const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0 &&
@@ -173,9 +175,9 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
           for (int u = 0; u < kStepUnroll; ++u) {
             const int j = ok[u] ? entry_j(ent[u]) : 0;  // masked visits read a staged atom
             jj[u] = j;
-            dx[u] = lx[j];
-            dy[u] = ly[j];
-            dz[u] = lz[j];
+            dx[u] = lp[3 * j];
+            dy[u] = lp[3 * j + 1];
+            dz[u] = lp[3 * j + 2];
           }
 #pragma unroll
           for (int u = 0; u < kStepUnroll; ++u) {
@@ -318,7 +320,10 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
 // Rebuild rows: one wavefront per atom; a workgroup of kRebuildWaves wavefronts handles that many
 // consecutive atoms of one flagged system ("chunks"; chunks_per_sys covers the largest system).
 constexpr int kRebuildWaves = 8;
-constexpr int kSurvCap = 2 * kWave;  // survivor queue of a wavefront in the wide path
+constexpr int kRebuildRowsPerWave = 1;  // rows a wavefront builds per staging of its system
+constexpr int kRebuildGrid = 512;       // workgroups of a rebuild launch (a grid-stride loop over chunks)
+constexpr int kSurvCap = 3 * kWave;  // survivor queue of a wavefront in the wide path
+constexpr int kStagePerThread = (kLdsMaxAtoms + kWave * kRebuildWaves - 1) / (kWave * kRebuildWaves);
 
 __device__ inline bool shift_ok(int S0, int S1, int S2) {
   // |S| <= 15 for all three: (S + 15) as unsigned is at most 30
@@ -342,7 +347,7 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
   uint32_t *__restrict__ nbr = a.nbr;
   for (int chunk = blockIdx.x; chunk < n_flag * chunks_per_sys; chunk += gridDim.x) {
     const int s = chunk == (int)blockIdx.x ? s_spec : a.list_cur[chunk / chunks_per_sys];
-    const int c0 = (chunk % chunks_per_sys) * kRebuildWaves;
+    const int c0 = (chunk % chunks_per_sys) * (kRebuildWaves * kRebuildRowsPerWave);
     const int64_t a0 = a.offs[s];
     const int ns = (int)(a.offs[s + 1] - a0);
     if (c0 >= ns) continue;  // uniform over the workgroup
@@ -380,20 +385,38 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
     float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns + (ns & 1));
     int *surv = reinterpret_cast<int *>(sf + ns) + wave * kSurvCap;
-    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
-      const double x = pin[a0 + k], y = pin[a.st_in + a0 + k], z = pin[2 * a.st_in + a0 + k];
-      lx[k] = x;
-      ly[k] = y;
-      lz[k] = z;
-      if (wide) {
-        const double f0 = x * i00 + y * i10 + z * i20, f1 = x * i01 + y * i11 + z * i21,
-                     f2 = x * i02 + y * i12 + z * i22;
-        sf[k] = make_float4((float)(f0 - floor(f0)), (float)(f1 - floor(f1)), (float)(f2 - floor(f2)), 0.0f);
+    {
+      // every load of the staging is issued before the first store (a thread holds at most
+      // kStagePerThread atoms; past the end it reloads the last atom and stores nothing)
+      double px[kStagePerThread], py[kStagePerThread], pz[kStagePerThread];
+#pragma unroll
+      for (int u = 0; u < kStagePerThread; ++u) {
+        const int k = threadIdx.x + u * kWave * kRebuildWaves;
+        const int kc = k < ns ? k : ns - 1;
+        px[u] = pin[a0 + kc];
+        py[u] = pin[a.st_in + a0 + kc];
+        pz[u] = pin[2 * a.st_in + a0 + kc];
+      }
+#pragma unroll
+      for (int u = 0; u < kStagePerThread; ++u) {
+        const int k = threadIdx.x + u * kWave * kRebuildWaves;
+        if (k >= ns) break;
+        const double x = px[u], y = py[u], z = pz[u];
+        lx[k] = x;
+        ly[k] = y;
+        lz[k] = z;
+        if (wide) {
+          const double f0 = x * i00 + y * i10 + z * i20, f1 = x * i01 + y * i11 + z * i21,
+                       f2 = x * i02 + y * i12 + z * i22;
+          sf[k] = make_float4((float)(f0 - floor(f0)), (float)(f1 - floor(f1)), (float)(f2 - floor(f2)), 0.0f);
+        }
       }
     }
     __syncthreads();
-    const int li = c0 + wave;
-    if (li >= ns) continue;  // uniform over the wavefront; no block barrier follows before the loop top
+    // wavefront w builds rows c0 + w, c0 + w + kRebuildWaves, ... of the chunk
+    for (int rr = 0; rr < kRebuildRowsPerWave; ++rr) {
+    const int li = c0 + wave + kRebuildWaves * rr;
+    if (li >= ns) break;  // uniform over the wavefront; no block barrier follows before the loop top
     const int64_t i = a0 + li;
     const double rx = lx[li], ry = ly[li], rz = lz[li];
     int cnt = 0;
@@ -440,8 +463,7 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
         if (in && p < a.max_nbr) nbr[row_index(p, i, st)] = pack_entry(j, s0, s1, s2);
         cnt += __popcll(m);
       };
-      for (int j0 = 0; j0 < ns; j0 += kWave) {
-        const int j = j0 + lane;
+      auto near_f32 = [&](int j) {  // float32 nearest-image test of candidate j (false past the end)
         const float4 fj = sf[j < ns ? j : li];
         float dfx = fj.x - fi.x, dfy = fj.y - fi.y, dfz = fj.z - fi.z;
         dfx -= rintf(dfx);
@@ -450,18 +472,29 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
         const float dx = dfx * g00 + dfy * g10 + dfz * g20;
         const float dy = dfx * g01 + dfy * g11 + dfz * g21;
         const float dz = dfx * g02 + dfy * g12 + dfz * g22;
-        const bool pass = (j < ns) & (dx * dx + dy * dy + dz * dz < rc2f);
-        const uint64_t m = __ballot(pass);
-        const int q = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-        if (pass) surv[q] = j;
-        pend += __popcll(m);
-        if (pend >= kWave) {
+        return (j < ns) & (dx * dx + dy * dy + dz * dz < rc2f);
+      };
+      // two blocks of 64 candidates per iteration (independent chains until their ballots); the
+      // queue holds up to 3 x 64 survivors, and every full 64 of them take the exact pass
+      for (int j0 = 0; j0 < ns; j0 += 2 * kWave) {
+        const int ja = j0 + lane, jb = j0 + kWave + lane;
+        const bool pa = near_f32(ja), pb = near_f32(jb);
+        const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+        const int qa = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0));
+        if (pa) surv[qa] = ja;
+        pend += __popcll(ma);
+        const int qb = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0));
+        if (pb) surv[qb] = jb;
+        pend += __popcll(mb);
+        while (pend >= kWave) {
           exact(kWave);
-          // move the overflow (fewer than 64 entries) to the front of the queue
+          // move the overflow (fewer than 2 x 64 entries) to the front of the queue
           const int rest = pend - kWave;
-          const int moved = lane < rest ? surv[kWave + lane] : 0;
+          const int m0 = lane < rest ? surv[kWave + lane] : 0;
+          const int m1 = lane + kWave < rest ? surv[2 * kWave + lane] : 0;
           __builtin_amdgcn_wave_barrier();
-          if (lane < rest) surv[lane] = moved;
+          if (lane < rest) surv[lane] = m0;
+          if (lane + kWave < rest) surv[kWave + lane] = m1;
           __builtin_amdgcn_wave_barrier();
           pend = rest;
         }
@@ -566,13 +599,14 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
       if (!(isfinite(rx) && isfinite(ry) && isfinite(rz))) status_raise(a.status, TS_STATUS_NONFINITE, 1);
     }
     if (__ballot(shift_bad) != 0 && lane == 0) status_raise(a.status, TS_STATUS_SHIFT, 1);
+    }  // rows of this wavefront
   }
 }
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st) {
-  const int chunks = (int)ceil_div(max_atoms, kRebuildWaves);
+  const int chunks = (int)ceil_div(max_atoms, kRebuildWaves * kRebuildRowsPerWave);
   const int64_t work = n_sys * chunks;
-  const unsigned grid = (unsigned)(work < 2048 ? work : 2048);
+  const unsigned grid = (unsigned)(work < kRebuildGrid ? work : kRebuildGrid);
   // float64 positions, float4 fractional coordinates (after one alignment double) and the
   // survivor queues (wide cells)
   const size_t shm = (size_t)(5 * max_atoms + 1) * sizeof(double) + sizeof(int) * kSurvCap * kRebuildWaves;
@@ -628,6 +662,8 @@ int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &
   rounds = rounds < 1 ? 1 : (rounds > max_rounds ? max_rounds : rounds);
   a.rounds = (int)rounds;
   a.chunks = (int)ceil_div(max_atoms, apb * rounds);
+  // equal shares of the largest system (the last chunk is not left with a remainder)
+  a.span = a.chunks > 0 ? (int)ceil_div(max_atoms, a.chunks) : 1;
   a.n_work = n_sys * a.chunks;
   const int64_t grid = ceil_div(a.n_work, kXcds) * kXcds;
   if (grid > 0x7fffffff) return TS_E_CAPACITY;

@@ -68,5 +68,44 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     return LIB_PATH
 
 
+# Build of the library with AddressSanitizer and UndefinedBehaviorSanitizer on the host code only
+# (the argument validation and launch planning of every entry point; each sanitizer flag is
+# restricted to the host pass, the device code is built as usual).  tests/test_host_sanitized.py
+# links a C driver of the host checks against it.
+SAN_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def build_host_sanitized(out_dir: str, jobs: int = 8) -> str:
+    os.makedirs(out_dir, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+    deps = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    newest_dep = max(os.path.getmtime(d) for d in deps)
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        if os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), newest_dep):
+            return obj  # up to date
+        cmd = [hipcc(), *HIP_FLAGS, "-g", *SAN_HOST_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"sanitized host compile failed for {src}:\n{res.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
+        objs = list(ex.map(one, srcs))
+    lib = os.path.join(out_dir, "libts_mi355x_hostsan.so")
+    clangxx = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clangxx):
+        clangxx = "/opt/rocm/llvm/bin/clang++"
+    cmd = [clangxx, "-shared", "-fsanitize=address,undefined", "-o", lib, *objs, "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{res.stderr}")
+    return lib
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

@@ -348,10 +348,12 @@ __global__ void __launch_bounds__(256) k_nl_enum(int64_t n, int64_t stride, cons
 
 NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   NlWork w;
-  char *p = static_cast<char *>(ws);
+  // offsets are accumulated as integers: ts_neighbor_workspace_bytes sizes the layout with ws = NULL
+  const uintptr_t base = reinterpret_cast<uintptr_t>(ws);
+  size_t off = 0;
   auto take = [&](size_t bytes) {
-    char *q = p;
-    p += (bytes + 255) & ~size_t(255);
+    char *q = reinterpret_cast<char *>(base + off);
+    off += (bytes + 255) & ~size_t(255);
     return q;
   };
   const int64_t nbins = 2 * n_atoms + n_sys;
@@ -368,7 +370,7 @@ NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   w.flags3 = reinterpret_cast<int32_t *>(take(4 * (6 * n_sys + 8)));
   w.pos4 = reinterpret_cast<double *>(take(32 * (n_atoms + 1)));
   w.adj_slots = reinterpret_cast<double *>(take(sizeof(double) * kAdjSlot * adj_slot_count(n_sys)));
-  w.bytes = static_cast<size_t>(p - static_cast<char *>(ws));
+  w.bytes = off;
   return w;
 }
 

@@ -461,6 +461,29 @@ def profile_kernels(api, torch, w, lanes, bin_factor, reps=20, copy_mib=256, gro
                 list_entries=int(nl.n_nbr.sum().item()), copy_bytes_each_way=n * 4, copy_launches=3)
 
 
+def profile_copper(api, torch, reps=20, copy_mib=256):
+    """Fixed launch sequence for rocprofv3 runs on the uneven 512-system copper batch: the pair-force
+    kernel ``reps`` times (its 290 MB list is beyond the Infinity Cache) and the calibration copy."""
+    from workloads import copper_uneven_batch
+    w = copper_uneven_batch(512, seed=2)
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, w.potential.cutoff, w.skin, bin_factor=2, margin=1.2)
+    pp = api.pair_params_from_spec(w.potential, w.pair_prec)
+    F = api.force_buffer(b, w.pair_prec)
+    for _ in range(reps):
+        api.ts_pair_forces(b, nl, pp, F)
+    n = copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    entries = int(nl.n_nbr.sum().item())
+    alg = b.n_atoms * (24 + 4 + 12) + 4 * entries + w.n_systems * (8 + 72)
+    return dict(mode="profile", workload="copper_morse_forces_512_uneven", n_atoms=b.n_atoms, force_launches=reps,
+                list_entries=entries, alg_bytes_per_launch=alg, copy_bytes_each_way=n * 4, copy_launches=3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -480,6 +503,8 @@ def main():
     ap.add_argument("--no-fire", action="store_true", help="skip the copper FIRE and soft-sphere workloads")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="run a short fixed launch sequence for rocprofv3 instead of the benchmark")
+    ap.add_argument("--profile-copper", action="store_true",
+                    help="fixed launch sequence of the copper force kernel for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (systems would shard "
@@ -493,6 +518,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     w = argon_batch(64, seed=1, n_steps=args.steps)
     log(f"workload {w.name}: {w.n_systems} systems, {w.n_atoms} atoms")
+    if args.profile_copper:
+        print(json.dumps(profile_copper(api, torch)), flush=True)
+        return
     if args.profile_kernels:
         print(json.dumps(profile_kernels(api, torch, w, args.lanes or 4, args.bin_factor, group=args.group)), flush=True)
         return

@@ -135,6 +135,19 @@ typedef struct {
   int64_t *status;     /* device int64[TS_STATUS_WORDS] */
   void *workspace;     /* device, ts_neighbor_workspace_bytes(N, S) bytes, caller-owned */
   size_t workspace_bytes;
+  /* Optional second row buffer (all three NULL, or all three set), used by the fused step loops
+     (ts_nve_step, ts_langevin_step and ts_nve_record on systems of at most 2048 atoms) to rebuild
+     lists one step ahead: a system whose rows are predicted to fail the validity bound at the next
+     step (2 (|r_{n+1} - ref| + 2 |r_{n+1} - r_n|) > skin, the factor 2 overridable by the
+     environment variable TS_DEFER_PREFACTOR) is rebuilt from r_n by extra workgroups of the next
+     step launch into the buffer it does not read there, and reads that buffer from the launch
+     after; a system whose rows do fail the bound is still rebuilt before the step that needs
+     them, as without the second buffer.  Forces and trajectories are identical with and without
+     it (pairs beyond the cutoff contribute exact zeros; rows are canonical).  On return every
+     system's rows, lengths and reference positions are back in nbr, n_nbr and ref_pos. */
+  int32_t *nbr_alt;     /* device, same shape as nbr */
+  int32_t *n_nbr_alt;   /* device [N] */
+  double *ref_pos_alt;  /* device SoA [3][stride] */
 } ts_neighbor_list;
 
 /* Bytes of device workspace a neighbor list needs for N atoms in S systems. */

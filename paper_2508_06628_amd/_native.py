@@ -82,6 +82,9 @@ class TsNeighborList(ctypes.Structure):
         ("status", c_void_p),
         ("workspace", c_void_p),
         ("workspace_bytes", c_size_t),
+        ("nbr_alt", c_void_p),
+        ("n_nbr_alt", c_void_p),
+        ("ref_pos_alt", c_void_p),
     ]
 
 

@@ -135,8 +135,11 @@ class NeighborList:
     """Padded neighbor list of a batch (rows of packed (j, S) entries, blocks of 8 per atom)."""
 
     def __init__(self, batch: Batch, cutoff: float, skin: float, max_nbr: int, bin_factor: int = 1, half: bool = False,
-                 lanes_per_atom: int = 0, group_atoms: int = 0):
+                 lanes_per_atom: int = 0, group_atoms: int = 0, deferred: bool = False):
         self.cutoff, self.skin, self.half, self.bin_factor = float(cutoff), float(skin), bool(half), int(bin_factor)
+        # second row buffer for the deferred rebuild of the fused step loops (systems up to 2048
+        # atoms, full lists); other batches would never use it
+        self.deferred = bool(deferred) and not self.half and 0 < batch.max_system_atoms <= 2048
         self.lanes_per_atom = int(lanes_per_atom)
         self.group_atoms = int(group_atoms)
         self.n_atoms, self.n_systems = batch.n_atoms, batch.n_systems
@@ -154,6 +157,12 @@ class NeighborList:
         self.status = torch.zeros(N.TS_STATUS_WORDS, dtype=torch.int64, device=dev)
         ws = int(N.lib().ts_neighbor_workspace_bytes(batch.n_atoms, batch.n_systems))
         self.workspace = torch.zeros(ws, dtype=torch.uint8, device=dev)
+        if self.deferred:
+            self.nbr_alt = torch.zeros_like(self.nbr)
+            self.n_nbr_alt = torch.zeros_like(self.n_nbr)
+            self.ref_pos_alt = torch.zeros_like(self.ref_pos)
+        else:
+            self.nbr_alt = self.n_nbr_alt = self.ref_pos_alt = None
 
     def struct(self) -> N.TsNeighborList:
         s = N.TsNeighborList()
@@ -171,6 +180,10 @@ class NeighborList:
         s.status = self.status.data_ptr()
         s.workspace = self.workspace.data_ptr()
         s.workspace_bytes = self.workspace.numel()
+        if self.deferred:
+            s.nbr_alt = self.nbr_alt.data_ptr()
+            s.n_nbr_alt = self.n_nbr_alt.data_ptr()
+            s.ref_pos_alt = self.ref_pos_alt.data_ptr()
         return s
 
     def read_status(self) -> np.ndarray:
@@ -203,10 +216,11 @@ def estimate_max_nbr(batch: Batch, r_list: float, margin: float = 1.3) -> int:
 
 def build_neighbor_list(batch: Batch, cutoff: float, skin: float, bin_factor: int = 1, max_nbr: Optional[int] = None,
                         margin: float = 1.25, half: bool = False, lanes_per_atom: int = 0,
-                        group_atoms: int = 0) -> NeighborList:
-    """Allocate and build a list, regrowing once if the first capacity guess was too small."""
+                        group_atoms: int = 0, deferred: bool = False) -> NeighborList:
+    """Allocate and build a list, regrowing once if the first capacity guess was too small.
+    ``deferred`` gives it the second row buffer of the deferred rebuild (fused step loops)."""
     guess = max_nbr or estimate_max_nbr(batch, cutoff + skin)
-    nl = NeighborList(batch, cutoff, skin, guess, bin_factor, half, lanes_per_atom, group_atoms)
+    nl = NeighborList(batch, cutoff, skin, guess, bin_factor, half, lanes_per_atom, group_atoms, deferred)
     ts_neighbor_build(batch, nl, force=True)
     st = nl.read_status()
     if st[N.TS_STATUS_NONFINITE] or st[N.TS_STATUS_SHIFT]:

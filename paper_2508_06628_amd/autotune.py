@@ -78,7 +78,8 @@ def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float
     cands = [(lanes, r * 256 // lanes) for lanes in choices for r in rounds if not (lanes == 1 and r > 1)]
     for lanes, group in cands:
         b = batch.clone()
-        trial = api.NeighborList(b, nl.cutoff, nl.skin, nl.max_nbr, nl.bin_factor, nl.half, lanes, group)
+        trial = api.NeighborList(b, nl.cutoff, nl.skin, nl.max_nbr, nl.bin_factor, nl.half, lanes, group,
+                                 nl.deferred)
         api.ts_neighbor_build(b, trial, force=True)
         F = api.force_buffer(b, prec)
         api.ts_pair_forces(b, trial, pp, F)

@@ -51,6 +51,8 @@ int validate_list(const ts_batch *b, const ts_neighbor_list *nl, bool need_works
                nl->lanes_per_atom == 4 || nl->lanes_per_atom == 8);
   TS_CHECK_ARG(nl->group_atoms >= 0 && nl->reserved == 0);
   TS_CHECK_ARG(nl->nbr && nl->n_nbr && nl->ref_pos && nl->ref_cell && nl->status);
+  const bool alt = nl->nbr_alt != nullptr;  // the second row buffer: all three pointers or none
+  TS_CHECK_ARG((nl->n_nbr_alt != nullptr) == alt && (nl->ref_pos_alt != nullptr) == alt);
   // the pair kernels address the entries with 32-bit byte offsets
   const int64_t stride = b->stride > 0 ? b->stride : b->n_atoms;
   if ((int64_t)((nl->max_nbr + 7) / 8) * (stride > 0 ? stride : 1) * 32 > (int64_t)UINT32_MAX) return TS_E_CAPACITY;

@@ -113,6 +113,7 @@ extern "C" int ts_langevin_step(const ts_batch *batch, ts_neighbor_list *nl, con
   ts::key_add(key, max_atoms);
   ts::key_add(key, force);
   ts::key_add(key, ts::fused_enabled());
+  ts::key_add(key, ts::defer_pre_factor());
   const ts::PairTable tab = ts::make_table(pp);
   return ts::run_graph_cached(use_graph != 0, key, ts::as_stream(stream), [&](hipStream_t s) {
     if (pp->prec == TS_PAIR_F32)

@@ -31,6 +31,8 @@ struct NlWork {
   int32_t *flags3;    // fused step loop: rebuild flags [3][S], flagged lists [3][S], counts [3]
   double *pos4;       // [N][4] positions packed per atom (x, y, z, unused) for neighbor gathers
   double *adj_slots;  // [adj_slot_count(S)][kAdjSlot] parameter-gradient partial sums (reverse loop, VJP)
+  int32_t *sel2;      // deferred rebuild: row buffer of each system [2][S] (launch parity)
+  int32_t *pflags3;   // deferred rebuild: pre-flags [3][S], pre-flagged lists [3][S], counts [3]
   size_t bytes;
 };
 

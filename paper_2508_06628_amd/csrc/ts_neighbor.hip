@@ -370,6 +370,8 @@ NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   w.flags3 = reinterpret_cast<int32_t *>(take(4 * (6 * n_sys + 8)));
   w.pos4 = reinterpret_cast<double *>(take(32 * (n_atoms + 1)));
   w.adj_slots = reinterpret_cast<double *>(take(sizeof(double) * kAdjSlot * adj_slot_count(n_sys)));
+  w.sel2 = reinterpret_cast<int32_t *>(take(4 * 2 * n_sys));
+  w.pflags3 = reinterpret_cast<int32_t *>(take(4 * (6 * n_sys + 8)));
   w.bytes = off;
   return w;
 }

@@ -1,6 +1,7 @@
 // Velocity-Verlet NVE over the whole batch (the molecular-dynamics integrators of the paper's
 // Abstract; every system advances in the same launches, Section 3), with the per-step neighbor
 // validity test and rebuild on the device and an optional hipGraph of the whole step loop.
+#include <cmath>
 #include <cstdlib>
 #include <string>
 
@@ -16,6 +17,13 @@ namespace ts {
 bool fused_enabled() {
   const char *e = std::getenv("TS_NVE_UNFUSED");
   return !(e && e[0] == '1');
+}
+
+double defer_pre_factor() {
+  const char *e = std::getenv("TS_DEFER_PREFACTOR");
+  if (!e || !e[0]) return 2.0;
+  const double v = std::atof(e);
+  return std::isfinite(v) && v >= 0.0 ? v : 2.0;
 }
 
 // v += (dt/2) a F / m ; r += dt v
@@ -159,6 +167,18 @@ int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable 
     a.lang = *lang;
     a.lang_adv = n_steps;
   }
+  // deferred rebuild when the list has its second row buffer: every system starts in buffer 0
+  const bool defer = nl->nbr_alt != nullptr;
+  if (defer) {
+    rc = fill_async<int32_t>(w.sel2, 2 * S, 0, st);
+    if (rc != TS_OK) return rc;
+    rc = fill_async<int32_t>(w.pflags3, 6 * S + 8, 0, st);
+    if (rc != TS_OK) return rc;
+    a.nbr_alt = reinterpret_cast<uint32_t *>(nl->nbr_alt);
+    a.n_nbr_alt = nl->n_nbr_alt;
+    a.ref_pos_alt = nl->ref_pos_alt;
+    a.pre_factor = defer_pre_factor();
+  }
   for (int step = 0; step <= n_steps; ++step) {
     const int mode = step == 0 ? (lang ? kStepLangFirst : kStepFirst)
                                : (step == n_steps ? kStepLast : (lang ? kStepLangMid : kStepMid));
@@ -188,11 +208,29 @@ int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable 
     }
     a.epot = mode == kStepLast ? epot : nullptr;
     a.virial = mode == kStepLast ? virial : nullptr;
+    if (defer) {
+      a.sel_cur = w.sel2 + S * (step % 2);
+      a.sel_next = w.sel2 + S * ((step + 1) % 2);
+      a.pflag_cur = w.pflags3 + S * (step % 3);
+      a.pflag_next = w.pflags3 + S * ((step + 1) % 3);
+      a.pflag_clear = w.pflags3 + S * ((step + 2) % 3);
+      a.plist_cur = w.pflags3 + 3 * S + S * (step % 3);
+      a.plist_next = w.pflags3 + 3 * S + S * ((step + 1) % 3);
+      a.pcount_cur = w.pflags3 + 6 * S + step % 3;
+      a.pcount_next = w.pflags3 + 6 * S + (step + 1) % 3;
+      a.pcount_clear = w.pflags3 + 6 * S + (step + 2) % 3;
+      a.n_defer_wgs = (mode == kStepMid || mode == kStepLangMid) ? kDeferWgs : 0;
+    }
     if (step != 0) {
       rc = launch_rebuild(a, S, max_atoms, st);
       if (rc != TS_OK) return rc;
     }
     rc = launch_step(mode, tl, nl->group_atoms, a, tab, prec, S, max_atoms, b->h_sys_offsets, st);
+    if (rc != TS_OK) return rc;
+  }
+  if (defer) {
+    // rows of systems rebuilt into the second buffer go back to the list's own buffer
+    rc = launch_rows_restore(a, w.sel2 + S * (n_steps % 2), S, st);
     if (rc != TS_OK) return rc;
   }
   if (ekin) {
@@ -244,6 +282,7 @@ extern "C" int ts_nve_step(const ts_batch *batch, ts_neighbor_list *nl, const ts
   ts::key_add(key, virial);
   const bool fused = ts::fused_enabled();
   ts::key_add(key, fused);
+  ts::key_add(key, ts::defer_pre_factor());
   return ts::run_graph_cached(use_graph != 0, key, ts::as_stream(stream), [&](hipStream_t s) {
     return ts::nve_sequence(batch, nl, pp, dt, accel, n_steps, force, epot, ekin, virial, max_atoms, s);
   });
@@ -268,6 +307,7 @@ extern "C" int ts_nve_record(const ts_batch *batch, ts_neighbor_list *nl, const 
   ts::key_add(key, max_atoms);
   ts::key_add(key, force);
   ts::key_add(key, traj);
+  ts::key_add(key, ts::defer_pre_factor());
   const ts::PairTable tab = ts::make_table(pp);
   return ts::run_graph_cached(use_graph != 0, key, ts::as_stream(stream), [&](hipStream_t s) {
     return ts::nve_fused_sequence(batch, nl, tab, pp->prec, dt, accel, n_steps, force, nullptr, nullptr, nullptr,

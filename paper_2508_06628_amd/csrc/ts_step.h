@@ -16,6 +16,9 @@ constexpr int kStepLangMid = 6;    // Langevin: forces, two half kicks, half dri
 constexpr int kStepThreads = 256;  // workgroup size of the step kernel
 constexpr int kStepUnroll = 4;      // row entries a lane evaluates together in the step kernel
 constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)
+constexpr int kDeferWgs = 256;      // rebuild workgroups of a step launch with the deferred rebuild
+constexpr int kDeferRowsPerWave = 4;  // rows a wavefront of those builds per staging of its system
+constexpr int kDeferSurvCap = 3 * 64;  // survivor queue of a rebuild wavefront (ints)
 
 struct StepArgs {
   const int64_t *offs;
@@ -50,6 +53,21 @@ struct StepArgs {
   int span;        // atoms per chunk: ceil(largest system / chunks) <= rounds * kStepThreads/TL
   int64_t n_work;  // n_systems * chunks (the grid is n_work rounded up to a multiple of kXcds)
   int n_sys;       // systems in the batch (rebuild launch)
+  // Deferred rebuild (the list has its second row buffer): a system whose rows will soon fail the
+  // validity bound is "pre-flagged" and rebuilt from r_n by extra workgroups of launch n (the first
+  // n_defer_wgs of the grid) into the buffer it does not use in launch n; from launch n + 1 on it
+  // reads that buffer.  sel_cur[s] / sel_next[s]: the buffer of system s in this / the next launch.
+  uint32_t *nbr_alt;
+  int32_t *n_nbr_alt;
+  double *ref_pos_alt;
+  const int32_t *sel_cur;
+  int32_t *sel_next;
+  int32_t *pflag_cur, *pflag_next, *pflag_clear;  // pre-flags of launches n-1 (rebuilt now), n, n+1
+  int32_t *plist_cur, *plist_next;
+  int32_t *pcount_cur, *pcount_next, *pcount_clear;
+  int n_defer_wgs;       // rebuild workgroups at the start of the grid (0: none in this launch)
+  int defer_chunks;      // chunks per system of those workgroups
+  double pre_factor;     // pre-flag when 2 (|r_{n+1} - ref| + pre_factor |r_{n+1} - r_n|) > skin
   // Langevin modes: O step of this launch (step index lang_k of the call) and, with a non-null
   // rng_step, the counter advance by lang_adv done by the call's last launch
   LangParams lang;
@@ -131,6 +149,12 @@ __device__ inline void image_range(double f, double reach, int *lo, int *hi, boo
 }
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st);
+
+// Copy back to the list's own buffer the rows of the systems with sel[s] = 1 (deferred rebuild).
+int launch_rows_restore(const StepArgs &a, const int32_t *sel, int64_t n_sys, hipStream_t st);
+
+// Pre-flag factor of the deferred rebuild: 2.0, or TS_DEFER_PREFACTOR from the environment.
+double defer_pre_factor();
 
 // Lanes per atom of the pair kernels: the list's choice, else 8 for batches too small to fill the
 // chip with 4 (fewer than 2048 wavefronts, i.e. under 32768 atoms), 4 otherwise.

@@ -33,8 +33,24 @@ __device__ inline void flag_system(const StepArgs &a, int s) {
   }
 }
 
+// Pre-flag system s for the deferred rebuild in the next launch (as flag_system, on the pre-flag
+// arrays).
+__device__ inline void preflag_system(const StepArgs &a, int s) {
+  if (__hip_atomic_load(&a.pflag_next[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  if (atomicExch(&a.pflag_next[s], 1) == 0) {
+    const int q = atomicAdd(a.pcount_next, 1);
+    if (q < a.n_sys) a.plist_next[q] = s;
+  }
+}
+
+template <int NW, int RPW, typename Target>
+__device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per_sys, const int32_t *list,
+                             const int32_t *count, Target target);
+
+// At least four waves per SIMD (at most 128 VGPRs) except in the once-per-call last mode: the
+// deferred-rebuild path shares the mid-step kernel's register budget with the pair loop.
 template <int KIND, typename T, int TL, int MODE>
-__global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a) {
+__global__ void __launch_bounds__(kStepThreads, MODE == kStepLast ? 1 : 4) k_step(PairTable tab, StepArgs a) {
   extern __shared__ double lds[];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   constexpr int APB = kStepThreads / TL;
@@ -43,7 +59,17 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   // Langevin: no launch after the call's last one reads the counter of this call
   if (MODE == kStepLast && a.lang.rng_step && blockIdx.x == 0 && threadIdx.x == 0)
     *a.lang.rng_step += (uint64_t)a.lang_adv;
-  const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
+  if constexpr (MID) {
+  if ((int)blockIdx.x < a.n_defer_wgs) {
+    // deferred rebuild: the systems pre-flagged by the previous launch, from r_n, into the row
+    // buffer each of them does not read in this launch (a multiple of kXcds workgroups, so the
+    // XCD of every force workgroup below is unchanged)
+    rebuild_rows<kStepThreads / kWave, kDeferRowsPerWave>(a, blockIdx.x, a.n_defer_wgs, a.defer_chunks, a.plist_cur,
+                                                          a.pcount_cur, [&](int q) { return 1 - a.sel_cur[q]; });
+    return;
+  }
+  }
+  const int wg = (int)xcd_order(blockIdx.x - a.n_defer_wgs, gridDim.x - a.n_defer_wgs);
   if (wg >= a.n_work) return;
   // uniform values: keep them in scalar registers (a vector division result would drag every
   // address derived from it into vector registers)
@@ -52,10 +78,24 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   // the flags and the list count of step n+2 (those of step n-1, consumed by the rebuild before
   // step n-1) are cleared here, ahead of every early exit: an empty system still clears its flag,
   // and workgroup 0 (system 0, chunk 0) the count, whatever the size of system 0
+  // with the deferred rebuild, the buffer of the next launch (switched when this launch rebuilds
+  // the system) and the pre-flag arrays of launch n+2 likewise
+  const bool defer = a.sel_cur != nullptr;  // uniform
+  const int sel = defer ? __builtin_amdgcn_readfirstlane(a.sel_cur[s]) : 0;
+  const bool fresh = MID && defer && __builtin_amdgcn_readfirstlane(a.pflag_cur[s]) != 0;
   if (MID && chunk == 0 && threadIdx.x == 0) {
     a.flag_clear[s] = 0;
     if (s == 0) *a.count_clear = 0;
+    if (defer) {
+      a.sel_next[s] = fresh ? 1 - sel : sel;
+      a.pflag_clear[s] = 0;
+      if (s == 0) *a.pcount_clear = 0;
+    }
   }
+  // this launch's rows, row lengths and reference positions of system s
+  const uint32_t *__restrict__ nbr = sel ? a.nbr_alt : a.nbr;
+  const int32_t *__restrict__ n_nbr = sel ? a.n_nbr_alt : a.n_nbr;
+  const double *__restrict__ ref_pos = sel ? a.ref_pos_alt : a.ref_pos;
   const int64_t a0 = a.offs[s];
   const int ns = (int)(a.offs[s + 1] - a0);
   const int first = chunk * a.span;
@@ -94,7 +134,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
         a.vel[c * a.st_vel + i] = v;
         a.pos_out[c * a.st_out + i] = rn[c];
       }
-      if (list_invalid(rn, a.ref_pos, a.st_vel, i, h, a.ref_cell + 9 * (int64_t)s, a.skin, a.r_list))
+      if (list_invalid(rn, ref_pos, a.st_vel, i, h, a.ref_cell + 9 * (int64_t)s, a.skin, a.r_list))
         flag_system(a, s);
     }
     return;
@@ -108,21 +148,18 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   // memory, so loads after it could not overlap the staging latency)
   struct AtomPre {
     int nn;
-    double v[3], sc, ref[3];
+    double v[3], sc;
   } pre = {};
   {
     const int li = first + grp;
     const bool own = li < end;
     const int64_t i = a0 + li;
-    pre.nn = own ? a.n_nbr[i] : 0;
+    pre.nn = own ? n_nbr[i] : 0;
     if (!FORCE_ONLY && own && lane == 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) pre.v[c] = a.vel[c * st + i];
       pre.sc = a.mass ? a.accel / a.mass[i] : a.accel;
-      if (MID) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) pre.ref[c] = a.ref_pos[c * st + i];
-      }
+
     }
   }
   // 1. stage r_n of the whole system, one (x, y, z) record per atom: a neighbor's three reads share
@@ -136,7 +173,6 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
   __syncthreads();
   const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                h22 = h[8];
-  const uint32_t *__restrict__ nbr = a.nbr;
 
   // 3. pair forces of this block's atoms, TL lanes per atom
   constexpr bool EV = MODE == kStepLast || MODE == kStepForceEV;
@@ -150,7 +186,7 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
     const bool own = li < end;
     const int64_t i = a0 + li;
     const double rx = own ? lp[3 * li] : 0.0, ry = own ? lp[3 * li + 1] : 0.0, rz = own ? lp[3 * li + 2] : 0.0;
-    const int nn = r == 0 ? pre.nn : (own ? a.n_nbr[i] : 0);
+    const int nn = r == 0 ? pre.nn : (own ? n_nbr[i] : 0);
     // (evaluated after the atom's own loads: this order keeps the register count of the loop low)
     const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0 &&
                       h00 > 0.0 && h11 > 0.0 && h22 > 0.0;
@@ -273,10 +309,18 @@ __global__ void __launch_bounds__(kStepThreads) k_step(PairTable tab, StepArgs a
         a.pos_out[a.st_out + i] = ny;
         a.pos_out[2 * a.st_out + i] = nz;
         // the cell is unchanged since the list was built (a changed cell was flagged by the first step)
-        const double qx = r == 0 ? pre.ref[0] : a.ref_pos[i], qy = r == 0 ? pre.ref[1] : a.ref_pos[st + i],
-                     qz = r == 0 ? pre.ref[2] : a.ref_pos[2 * st + i];
-        const double dx = nx - qx, dy = ny - qy, dz = nz - qz;
-        if (bound_exceeded(sqrt(norm2(dx, dy, dz)), 0.0, a.skin, a.r_list)) flag_system(a, s);
+        // (rows rebuilt from r_n in this launch have the reference r_n)
+        const double qx = fresh ? rx : ref_pos[i], qy = fresh ? ry : ref_pos[st + i],
+                     qz = fresh ? rz : ref_pos[2 * st + i];
+        const double dref = sqrt(norm2(nx - qx, ny - qy, nz - qz));
+        if (bound_exceeded(dref, 0.0, a.skin, a.r_list)) {
+          flag_system(a, s);  // the list of the next launch fails: rebuilt before it
+        } else if (defer && !fresh) {
+          // predicted to fail soon (the displacement since the build grows by about one step's
+          // displacement per step): rebuilt during the next launch, which still reads valid rows
+          const double dstep = sqrt(norm2(nx - rx, ny - ry, nz - rz));
+          if (bound_exceeded(dref + a.pre_factor * dstep, 0.0, a.skin, a.r_list)) preflag_system(a, s);
+        }
       } else {
         F[i] = Fx;
         F[st + i] = Fy;
@@ -323,7 +367,6 @@ constexpr int kRebuildWaves = 8;
 constexpr int kRebuildRowsPerWave = 1;  // rows a wavefront builds per staging of its system
 constexpr int kRebuildGrid = 512;       // workgroups of a rebuild launch (a grid-stride loop over chunks)
 constexpr int kSurvCap = 3 * kWave;  // survivor queue of a wavefront in the wide path
-constexpr int kStagePerThread = (kLdsMaxAtoms + kWave * kRebuildWaves - 1) / (kWave * kRebuildWaves);
 
 __device__ inline bool shift_ok(int S0, int S1, int S2) {
   // |S| <= 15 for all three: (S + 15) as unsigned is at most 30
@@ -332,25 +375,37 @@ __device__ inline bool shift_ok(int S0, int S1, int S2) {
          ((unsigned)(S2 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT);
 }
 
-__global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs a, int chunks_per_sys) {
+// The rows of the systems in list[0 .. *count) from positions a.pos_in, built by workgroup wg of
+// n_wg (a grid-stride loop over chunks of NW * RPW consecutive atoms of one system; chunks_per_sys
+// covers the largest system).  Each system's rows, row lengths and reference positions go to the
+// buffer `target(s)` selects (0: nbr, n_nbr, ref_pos; 1: the deferred-rebuild buffers).
+template <int NW, int RPW, typename Target>
+__device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per_sys, const int32_t *list,
+                             const int32_t *count, Target target) {
   extern __shared__ double lds[];
+  // atoms a thread stages: batches of kStageBatch, every load of a batch issued before its stores
+  constexpr int kStageBatch = 4;
+  constexpr int kStage = (kLdsMaxAtoms + kWave * NW - 1) / (kWave * NW);
   // the flagged-system count and this workgroup's first list slot are loaded together (the slot
   // is read speculatively: the list has room for every system)
-  const int q0 = blockIdx.x / chunks_per_sys;
-  const int s_spec = q0 < a.n_sys ? a.list_cur[q0] : 0;
-  const int n_cnt = *a.count_cur;
+  const int q0 = wg / chunks_per_sys;
+  const int s_spec = q0 < a.n_sys ? list[q0] : 0;
+  const int n_cnt = *count;
   const int n_flag = n_cnt < a.n_sys ? n_cnt : a.n_sys;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const double rl2 = a.r_list * a.r_list;
   const int64_t st = a.st_vel;
   const double *__restrict__ pin = a.pos_in;
-  uint32_t *__restrict__ nbr = a.nbr;
-  for (int chunk = blockIdx.x; chunk < n_flag * chunks_per_sys; chunk += gridDim.x) {
-    const int s = chunk == (int)blockIdx.x ? s_spec : a.list_cur[chunk / chunks_per_sys];
-    const int c0 = (chunk % chunks_per_sys) * (kRebuildWaves * kRebuildRowsPerWave);
+  for (int chunk = wg; chunk < n_flag * chunks_per_sys; chunk += n_wg) {
+    const int s = chunk == wg ? s_spec : list[chunk / chunks_per_sys];
+    const int c0 = (chunk % chunks_per_sys) * (NW * RPW);
     const int64_t a0 = a.offs[s];
     const int ns = (int)(a.offs[s + 1] - a0);
     if (c0 >= ns) continue;  // uniform over the workgroup
+    const int buf = __builtin_amdgcn_readfirstlane(target(s));
+    uint32_t *__restrict__ nbr = buf ? a.nbr_alt : a.nbr;
+    int32_t *__restrict__ n_nbr = buf ? a.n_nbr_alt : a.n_nbr;
+    double *__restrict__ ref_pos = buf ? a.ref_pos_alt : a.ref_pos;
     const double *__restrict__ h = a.cell + 9 * (int64_t)s;
     if (c0 == 0) {
       if (threadIdx.x < 9) a.ref_cell[9 * (int64_t)s + threadIdx.x] = h[threadIdx.x];
@@ -386,20 +441,23 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns + (ns & 1));
     int *surv = reinterpret_cast<int *>(sf + ns) + wave * kSurvCap;
     {
-      // every load of the staging is issued before the first store (a thread holds at most
-      // kStagePerThread atoms; past the end it reloads the last atom and stores nothing)
-      double px[kStagePerThread], py[kStagePerThread], pz[kStagePerThread];
+      // the loads of a batch are issued before its stores (past the end a thread reloads the last
+      // atom and stores nothing)
+#pragma unroll 1
+      for (int u0 = 0; u0 < kStage && u0 * kWave * NW < ns; u0 += kStageBatch) {
+      double px[kStageBatch], py[kStageBatch], pz[kStageBatch];
 #pragma unroll
-      for (int u = 0; u < kStagePerThread; ++u) {
-        const int k = threadIdx.x + u * kWave * kRebuildWaves;
+      for (int v = 0; v < kStageBatch; ++v) {
+        const int k = threadIdx.x + (u0 + v) * kWave * NW;
         const int kc = k < ns ? k : ns - 1;
-        px[u] = pin[a0 + kc];
-        py[u] = pin[a.st_in + a0 + kc];
-        pz[u] = pin[2 * a.st_in + a0 + kc];
+        px[v] = pin[a0 + kc];
+        py[v] = pin[a.st_in + a0 + kc];
+        pz[v] = pin[2 * a.st_in + a0 + kc];
       }
 #pragma unroll
-      for (int u = 0; u < kStagePerThread; ++u) {
-        const int k = threadIdx.x + u * kWave * kRebuildWaves;
+      for (int v = 0; v < kStageBatch; ++v) {
+        const int u = v;
+        const int k = threadIdx.x + (u0 + v) * kWave * NW;
         if (k >= ns) break;
         const double x = px[u], y = py[u], z = pz[u];
         lx[k] = x;
@@ -411,11 +469,13 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
           sf[k] = make_float4((float)(f0 - floor(f0)), (float)(f1 - floor(f1)), (float)(f2 - floor(f2)), 0.0f);
         }
       }
+      }  // batches
     }
     __syncthreads();
     // wavefront w builds rows c0 + w, c0 + w + kRebuildWaves, ... of the chunk
-    for (int rr = 0; rr < kRebuildRowsPerWave; ++rr) {
-    const int li = c0 + wave + kRebuildWaves * rr;
+#pragma unroll 1
+    for (int rr = 0; rr < RPW; ++rr) {
+    const int li = c0 + wave + NW * rr;
     if (li >= ns) break;  // uniform over the wavefront; no block barrier follows before the loop top
     const int64_t i = a0 + li;
     const double rx = lx[li], ry = ly[li], rz = lz[li];
@@ -590,10 +650,10 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
       cnt += total;
     }
     if (lane == 0) {
-      a.n_nbr[i] = cnt < a.max_nbr ? cnt : a.max_nbr;
-      a.ref_pos[i] = rx;
-      a.ref_pos[st + i] = ry;
-      a.ref_pos[2 * st + i] = rz;
+      n_nbr[i] = cnt < a.max_nbr ? cnt : a.max_nbr;
+      ref_pos[i] = rx;
+      ref_pos[st + i] = ry;
+      ref_pos[2 * st + i] = rz;
       status_raise(a.status, TS_STATUS_MAX_NBR, cnt);
       if (cnt > a.max_nbr) status_raise(a.status, TS_STATUS_OVERFLOW, 1);
       if (!(isfinite(rx) && isfinite(ry) && isfinite(rz))) status_raise(a.status, TS_STATUS_NONFINITE, 1);
@@ -601,6 +661,13 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
     if (__ballot(shift_bad) != 0 && lane == 0) status_raise(a.status, TS_STATUS_SHIFT, 1);
     }  // rows of this wavefront
   }
+}
+
+// Rows of the systems flagged for a rebuild before the next step (the list's own buffer of each
+// system: the one the step kernel reads next).
+__global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs a, int chunks_per_sys) {
+  rebuild_rows<kRebuildWaves, kRebuildRowsPerWave>(a, blockIdx.x, gridDim.x, chunks_per_sys, a.list_cur, a.count_cur,
+                                                   [&](int s) { return a.sel_cur ? a.sel_cur[s] : 0; });
 }
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st) {
@@ -665,15 +732,52 @@ int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &
   // equal shares of the largest system (the last chunk is not left with a remainder)
   a.span = a.chunks > 0 ? (int)ceil_div(max_atoms, a.chunks) : 1;
   a.n_work = n_sys * a.chunks;
-  const int64_t grid = ceil_div(a.n_work, kXcds) * kXcds;
+  // deferred-rebuild workgroups first (a multiple of kXcds), then the force workgroups
+  const int64_t grid = ceil_div(a.n_work, kXcds) * kXcds + a.n_defer_wgs;
   if (grid > 0x7fffffff) return TS_E_CAPACITY;
   const dim3 g((unsigned)grid);
-  const size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
+  size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
+  if (a.n_defer_wgs > 0) {
+    constexpr int nw = kStepThreads / kWave;
+    a.defer_chunks = (int)ceil_div(max_atoms, nw * kDeferRowsPerWave);
+    const size_t shm_rb = (size_t)(5 * max_atoms + 1) * sizeof(double) + sizeof(int) * kSurvCap * nw;
+    shm = shm_rb > shm ? shm_rb : shm;
+  }
   with_kind(t.kind, [&](auto k) {
     constexpr int KIND = decltype(k)::value;
     if (prec == TS_PAIR_F32) launch_step_kt<KIND, float>(tl, mode, a, t, g, shm, st);
     else launch_step_kt<KIND, double>(tl, mode, a, t, g, shm, st);
   });
+  TS_LAUNCH_CHECK();
+  return TS_OK;
+}
+
+// After a loop with the deferred rebuild: the rows, row lengths and reference positions of every
+// system whose current rows are in the second buffer (sel[s] = 1) are copied back to the list's
+// own buffer, where every other entry point reads them (one workgroup per system).
+__global__ void __launch_bounds__(256) k_rows_restore(StepArgs a, const int32_t *__restrict__ sel, int n_blocks) {
+  const int s = blockIdx.x;
+  if (sel[s] == 0) return;
+  const int64_t a0 = a.offs[s], ns = a.offs[s + 1] - a0, st = a.st_vel;
+  const int64_t n_rows = ns * n_blocks * kRowBlock;
+  for (int64_t t = threadIdx.x; t < n_rows; t += blockDim.x) {
+    const int64_t w = t % kRowBlock, r = t / kRowBlock;
+    const int64_t idx = ((r / ns) * st + a0 + r % ns) * kRowBlock + w;
+    a.nbr[idx] = a.nbr_alt[idx];
+  }
+  for (int64_t k = threadIdx.x; k < ns; k += blockDim.x) {
+    const int64_t i = a0 + k;
+    a.n_nbr[i] = a.n_nbr_alt[i];
+    a.ref_pos[i] = a.ref_pos_alt[i];
+    a.ref_pos[st + i] = a.ref_pos_alt[st + i];
+    a.ref_pos[2 * st + i] = a.ref_pos_alt[2 * st + i];
+  }
+}
+
+int launch_rows_restore(const StepArgs &a, const int32_t *sel, int64_t n_sys, hipStream_t st) {
+  if (n_sys <= 0) return TS_OK;
+  hipLaunchKernelGGL(k_rows_restore, dim3((unsigned)n_sys), dim3(256), 0, st, a, sel,
+                     (int)ceil_div(a.max_nbr, kRowBlock));
   TS_LAUNCH_CHECK();
   return TS_OK;
 }

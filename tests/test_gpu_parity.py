@@ -326,13 +326,14 @@ def test_rdf_and_vjp():
 # ----------------------------------------------------------------------------- fused step loop
 
 
-def _run_nve(w, prec, steps, lanes, unfused, use_graph=True):
+def _run_nve(w, prec, steps, lanes, unfused, use_graph=True, deferred=False):
     import os
     api = _api()
     os.environ["TS_NVE_UNFUSED"] = "1" if unfused else "0"
     try:
         b = _batch(w)
-        nl = api.build_neighbor_list(b, w.potential.cutoff, w.skin, bin_factor=2, lanes_per_atom=lanes)
+        nl = api.build_neighbor_list(b, w.potential.cutoff, w.skin, bin_factor=2, lanes_per_atom=lanes,
+                                     deferred=deferred)
         pp = api.pair_params_from_spec(w.potential, prec)
         F, _, _ = api.compute_forces(b, nl, pp, prec)
         E = torch.zeros(w.n_systems, dtype=torch.float64, device="cuda")
@@ -348,11 +349,15 @@ def _run_nve(w, prec, steps, lanes, unfused, use_graph=True):
 def test_fused_step_equals_multikernel_step():
     w = argon_batch(3, seed=21, reps=(4, 4, 4))
     ref = _run_nve(w, "f32", 40, 1, unfused=True)
-    one = _run_nve(w, "f32", 40, 1, unfused=False)
+    one = _run_nve(w, "f32", 40, 1, unfused=False, deferred=False)
+    one_d = _run_nve(w, "f32", 40, 1, unfused=False, deferred=True)
     four = _run_nve(w, "f32", 40, 4, unfused=False)
-    # one lane per atom sums each row in the same order: bit-identical trajectory and lists
-    assert torch.equal(ref[0].pos, one[0].pos) and torch.equal(ref[0].vel, one[0].vel)
-    assert torch.equal(ref[2], one[2])
+    # one lane per atom sums each row in the same order: bit-identical trajectory, and with the
+    # synchronous rebuild the same lists (the deferred rebuild builds some lists a step earlier:
+    # other reference positions, the same trajectory)
+    for run in (one, one_d):
+        assert torch.equal(ref[0].pos, run[0].pos) and torch.equal(ref[0].vel, run[0].vel)
+        assert torch.equal(ref[2], run[2])
     assert torch.equal(ref[1].n_nbr, one[1].n_nbr)
     assert ref[1].read_status()[2] == one[1].read_status()[2]
     # four lanes per atom change only the float64 summation order of each row

@@ -136,13 +136,14 @@ def graph_export(api, torch, w, bin_factor, reps=50):
                 frac_hbm=round(alg / (us * 1e-6) / 8e12, 4))
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by a device copy of known size), or None once the kernel sources have
-    changed since those counters were taken."""
+def measured_counter(summary: str, field: str, kernel: str):
+    """A per-launch figure of ``kernel`` from a committed rocprofv3 counter summary under profiles/
+    (``traffic_bytes_per_launch``: FETCH_SIZE + WRITE_SIZE scaled by a device copy of known size;
+    ``valu_insts_per_launch``: SQ_INSTS_VALU), or None once the kernel sources have changed since
+    those counters were taken."""
     import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_step_argon_64x864_counters.txt")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         lines = open(path).read().splitlines()
     except OSError:
@@ -154,8 +155,25 @@ def measured_traffic(kernel: str):
     rec = dict(l.split(": ", 1) for l in lines if ": " in l and not l.startswith("#"))
     if rec.get("csrc_sha256") != h.hexdigest():
         return None
-    v = rec.get(f"traffic_bytes_per_launch {kernel}")
+    v = rec.get(f"{field} {kernel}")
     return int(v) if v else None
+
+
+# VALU issue peak of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second
+# (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles; float64 FMA issues at this rate)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def alu_roofline(summary: str, kernel: str, avg_us: float):
+    """The kernel's VALU lane-instruction rate (committed SQ_INSTS_VALU per launch x 64 lanes ÷ the
+    live average launch duration) against the chip's VALU issue peak, or None without counters."""
+    n = measured_counter(summary, "valu_insts_per_launch", kernel)
+    if n is None:
+        return None
+    achieved = n * 64 / (avg_us * 1e-6)
+    return dict(bound="alu", achieved=round(achieved / 1e12, 2), peak=round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                unit="T lane-instructions/s", frac=round(achieved / VALU_PEAK_LANE_OPS, 4), kernel=kernel,
+                valu_insts_per_launch=n)
 
 
 def force_kernel_roofline(api, torch, r, reps=200):
@@ -164,6 +182,10 @@ def force_kernel_roofline(api, torch, r, reps=200):
     LDS (up to 2048 atoms) the force entry point runs the step kernel in its forces-only mode: one
     workgroup per system, positions staged in LDS."""
     b, nl, pp, F = r["batch"], r["nl"], r["pp"], r["F"]
+    # four lanes per atom, the configuration of the committed counter summaries (the step loop
+    # keeps the autotuner's choice)
+    tuned = nl.lanes_per_atom, nl.group_atoms
+    nl.lanes_per_atom, nl.group_atoms = 4, 0
     stream = torch.cuda.current_stream()
     for _ in range(10):
         api.ts_pair_forces(b, nl, pp, F, stream=stream)
@@ -175,6 +197,7 @@ def force_kernel_roofline(api, torch, r, reps=200):
     e1.record(stream)
     torch.cuda.synchronize()
     avg_ms = e0.elapsed_time(e1) / reps
+    nl.lanes_per_atom, nl.group_atoms = tuned
     n, n_sys = b.n_atoms, b.n_systems
     entries = int(nl.n_nbr.sum().item())
     fbytes = 4 if F.dtype == torch.float32 else 8
@@ -182,11 +205,13 @@ def force_kernel_roofline(api, torch, r, reps=200):
     # per system: atom offset 8 B and cell 72 B
     alg = n * (24 + 4 + 3 * fbytes) + 4 * entries + n_sys * (8 + 72)
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    tl = nl.lanes_per_atom if nl.lanes_per_atom > 0 else 4
+    tl = 4
     ftype = "float" if fbytes == 4 else "double"
     kernel = f"ts::k_step<0, {ftype}, {tl}, 3>"
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kernel),
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=measured_counter("k_step_argon_64x864_counters.txt", "traffic_bytes_per_launch",
+                                         "void " + kernel),
                 kernel=kernel, avg_launch_us=round(avg_ms * 1e3, 3),
                 launches_timed=reps, alg_bytes_per_launch=alg, alg_bytes_per_atom=round(alg / n, 1),
                 mean_list_len=round(entries / n, 2))
@@ -327,9 +352,14 @@ def copper_force_roofline(api, torch, reps=50):
     alg = n * (24 + 4 + 12) + 4 * entries + w.n_systems * (8 + 72)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     tl = nl.lanes_per_atom if nl.lanes_per_atom > 0 else (8 if n * 4 // 64 < 2048 else 4)
-    return dict(workload=f"copper_morse_forces_{w.n_systems}_uneven", kernel=f"ts::k_step<1, float, {tl}, 3>",
+    kernel = f"ts::k_step<1, float, {tl}, 3>"
+    return dict(workload=f"copper_morse_forces_{w.n_systems}_uneven", kernel=kernel,
                 bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), avg_launch_us=round(avg_ms * 1e3, 2),
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=measured_counter("k_step_copper_512_counters.txt", "traffic_bytes_per_launch",
+                                         "void " + kernel),
+                roofline_alu=alu_roofline("k_step_copper_512_counters.txt", "void " + kernel, avg_ms * 1e3),
+                avg_launch_us=round(avg_ms * 1e3, 2),
                 alg_bytes_per_launch=alg, list_entries=entries, mean_list_len=round(entries / n, 2), n_atoms=n)
 
 
@@ -558,6 +588,8 @@ def main():
                    "list_capacity": r["capacity"], "max_list_len": r["max_nbr"], "system_rebuilds": r["rebuilds"],
                    "wall_s": round(r["wall_s"], 4)},
         "roofline": roof,
+        "roofline_alu": alu_roofline("k_step_argon_64x864_counters.txt", "void " + roof["kernel"],
+                                     roof["avg_launch_us"]),
         "roofline_whole_step": step_roof,
     }
     if not args.no_plain:

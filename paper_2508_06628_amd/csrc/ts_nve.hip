@@ -180,8 +180,8 @@ int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable 
     a.pre_factor = defer_pre_factor();
   }
   for (int step = 0; step <= n_steps; ++step) {
-    const int mode = step == 0 ? (lang ? kStepLangFirst : kStepFirst)
-                               : (step == n_steps ? kStepLast : (lang ? kStepLangMid : kStepMid));
+    const int mid = defer ? (lang ? kStepLangMidDefer : kStepMidDefer) : (lang ? kStepLangMid : kStepMid);
+    const int mode = step == 0 ? (lang ? kStepLangFirst : kStepFirst) : (step == n_steps ? kStepLast : mid);
     a.lang_k = step;
     a.pos_in = buf[step % 2];
     a.st_in = sts[step % 2];
@@ -219,7 +219,7 @@ int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable 
       a.pcount_cur = w.pflags3 + 6 * S + step % 3;
       a.pcount_next = w.pflags3 + 6 * S + (step + 1) % 3;
       a.pcount_clear = w.pflags3 + 6 * S + (step + 2) % 3;
-      a.n_defer_wgs = (mode == kStepMid || mode == kStepLangMid) ? kDeferWgs : 0;
+      a.n_defer_wgs = (mode == kStepMidDefer || mode == kStepLangMidDefer) ? kDeferWgs : 0;
     }
     if (step != 0) {
       rc = launch_rebuild(a, S, max_atoms, st);

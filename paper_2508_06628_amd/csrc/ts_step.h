@@ -13,6 +13,8 @@ constexpr int kStepForce = 3;  // forces only (ts_pair_forces)
 constexpr int kStepForceEV = 4;  // forces, energy and virial (ts_pair_forces)
 constexpr int kStepLangFirst = 5;  // Langevin: first half kick, half drift, O step, half drift
 constexpr int kStepLangMid = 6;    // Langevin: forces, two half kicks, half drift, O step, half drift, validity
+constexpr int kStepMidDefer = 7;      // kStepMid with the deferred rebuild (second row buffer)
+constexpr int kStepLangMidDefer = 8;  // kStepLangMid with the deferred rebuild
 constexpr int kStepThreads = 256;  // workgroup size of the step kernel
 constexpr int kStepUnroll = 4;      // row entries a lane evaluates together in the step kernel
 constexpr int kLdsMaxAtoms = 2048;  // largest system staged in LDS (3 x 8 B x atoms = 48 KiB)

@@ -47,19 +47,21 @@ template <int NW, int RPW, typename Target>
 __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per_sys, const int32_t *list,
                              const int32_t *count, Target target);
 
-// At least four waves per SIMD (at most 128 VGPRs) except in the once-per-call last mode: the
-// deferred-rebuild path shares the mid-step kernel's register budget with the pair loop.
+// The deferred-rebuild modes keep at least four waves per SIMD (at most 128 VGPRs): their rebuild
+// path shares the kernel's register budget with the pair loop.
 template <int KIND, typename T, int TL, int MODE>
-__global__ void __launch_bounds__(kStepThreads, MODE == kStepLast ? 1 : 4) k_step(PairTable tab, StepArgs a) {
+__global__ void __launch_bounds__(kStepThreads, MODE == kStepMidDefer || MODE == kStepLangMidDefer ? 4 : 1)
+    k_step(PairTable tab, StepArgs a) {
   extern __shared__ double lds[];
   __shared__ PairCoef ltab[TS_MAX_SPECIES * TS_MAX_SPECIES];
   constexpr int APB = kStepThreads / TL;
-  constexpr bool LANG = MODE == kStepLangFirst || MODE == kStepLangMid;
-  constexpr bool MID = MODE == kStepMid || MODE == kStepLangMid;
+  constexpr bool LANG = MODE == kStepLangFirst || MODE == kStepLangMid || MODE == kStepLangMidDefer;
+  constexpr bool DEFER = MODE == kStepMidDefer || MODE == kStepLangMidDefer;
+  constexpr bool MID = MODE == kStepMid || MODE == kStepLangMid || DEFER;
   // Langevin: no launch after the call's last one reads the counter of this call
   if (MODE == kStepLast && a.lang.rng_step && blockIdx.x == 0 && threadIdx.x == 0)
     *a.lang.rng_step += (uint64_t)a.lang_adv;
-  if constexpr (MID) {
+  if constexpr (DEFER) {
   if ((int)blockIdx.x < a.n_defer_wgs) {
     // deferred rebuild: the systems pre-flagged by the previous launch, from r_n, into the row
     // buffer each of them does not read in this launch (a multiple of kXcds workgroups, so the
@@ -80,13 +82,14 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepLast ? 1 : 4) k_ste
   // and workgroup 0 (system 0, chunk 0) the count, whatever the size of system 0
   // with the deferred rebuild, the buffer of the next launch (switched when this launch rebuilds
   // the system) and the pre-flag arrays of launch n+2 likewise
+  // (the last and forces-only modes of a deferred loop read the buffer too)
   const bool defer = a.sel_cur != nullptr;  // uniform
   const int sel = defer ? __builtin_amdgcn_readfirstlane(a.sel_cur[s]) : 0;
-  const bool fresh = MID && defer && __builtin_amdgcn_readfirstlane(a.pflag_cur[s]) != 0;
+  const bool fresh = DEFER && __builtin_amdgcn_readfirstlane(a.pflag_cur[s]) != 0;
   if (MID && chunk == 0 && threadIdx.x == 0) {
     a.flag_clear[s] = 0;
     if (s == 0) *a.count_clear = 0;
-    if (defer) {
+    if (DEFER) {
       a.sel_next[s] = fresh ? 1 - sel : sel;
       a.pflag_clear[s] = 0;
       if (s == 0) *a.pcount_clear = 0;
@@ -148,7 +151,7 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepLast ? 1 : 4) k_ste
   // memory, so loads after it could not overlap the staging latency)
   struct AtomPre {
     int nn;
-    double v[3], sc;
+    double v[3], sc, ref[3];
   } pre = {};
   {
     const int li = first + grp;
@@ -159,7 +162,10 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepLast ? 1 : 4) k_ste
 #pragma unroll
       for (int c = 0; c < 3; ++c) pre.v[c] = a.vel[c * st + i];
       pre.sc = a.mass ? a.accel / a.mass[i] : a.accel;
-
+      if (MID && !DEFER) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pre.ref[c] = ref_pos[c * st + i];
+      }
     }
   }
   // 1. stage r_n of the whole system, one (x, y, z) record per atom: a neighbor's three reads share
@@ -310,12 +316,20 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepLast ? 1 : 4) k_ste
         a.pos_out[2 * a.st_out + i] = nz;
         // the cell is unchanged since the list was built (a changed cell was flagged by the first step)
         // (rows rebuilt from r_n in this launch have the reference r_n)
-        const double qx = fresh ? rx : ref_pos[i], qy = fresh ? ry : ref_pos[st + i],
-                     qz = fresh ? rz : ref_pos[2 * st + i];
+        double qx, qy, qz;
+        if (DEFER) {
+          qx = fresh ? rx : ref_pos[i];
+          qy = fresh ? ry : ref_pos[st + i];
+          qz = fresh ? rz : ref_pos[2 * st + i];
+        } else {
+          qx = r == 0 ? pre.ref[0] : ref_pos[i];
+          qy = r == 0 ? pre.ref[1] : ref_pos[st + i];
+          qz = r == 0 ? pre.ref[2] : ref_pos[2 * st + i];
+        }
         const double dref = sqrt(norm2(nx - qx, ny - qy, nz - qz));
         if (bound_exceeded(dref, 0.0, a.skin, a.r_list)) {
           flag_system(a, s);  // the list of the next launch fails: rebuilt before it
-        } else if (defer && !fresh) {
+        } else if (DEFER && !fresh) {
           // predicted to fail soon (the displacement since the build grows by about one step's
           // displacement per step): rebuilt during the next launch, which still reads valid rows
           const double dstep = sqrt(norm2(nx - rx, ny - ry, nz - rz));
@@ -694,6 +708,10 @@ static void launch_step_k(int mode, const StepArgs &a, const PairTable &t, dim3 
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLangMid>), g, dim3(kStepThreads), shm, st, t, a);
   else if (mode == kStepMid)
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepMid>), g, dim3(kStepThreads), shm, st, t, a);
+  else if (mode == kStepMidDefer)
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepMidDefer>), g, dim3(kStepThreads), shm, st, t, a);
+  else if (mode == kStepLangMidDefer)
+    hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLangMidDefer>), g, dim3(kStepThreads), shm, st, t, a);
   else if (mode == kStepLast)
     hipLaunchKernelGGL((k_step<KIND, T, TL, kStepLast>), g, dim3(kStepThreads), shm, st, t, a);
   else if (mode == kStepForce)

@@ -33,6 +33,7 @@ struct NlWork {
   double *adj_slots;  // [adj_slot_count(S)][kAdjSlot] parameter-gradient partial sums (reverse loop, VJP)
   int32_t *sel2;      // deferred rebuild: row buffer of each system [2][S] (launch parity)
   int32_t *pflags3;   // deferred rebuild: pre-flags [3][S], pre-flagged lists [3][S], counts [3]
+  double *row_geom;   // fused step loops: per-system cell geometry of the rebuilds [S][14]
   size_t bytes;
 };
 

@@ -372,6 +372,7 @@ NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   w.adj_slots = reinterpret_cast<double *>(take(sizeof(double) * kAdjSlot * adj_slot_count(n_sys)));
   w.sel2 = reinterpret_cast<int32_t *>(take(4 * 2 * n_sys));
   w.pflags3 = reinterpret_cast<int32_t *>(take(4 * (6 * n_sys + 8)));
+  w.row_geom = reinterpret_cast<double *>(take(sizeof(double) * 14 * n_sys));
   w.bytes = off;
   return w;
 }

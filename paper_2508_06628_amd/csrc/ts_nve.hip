@@ -167,6 +167,11 @@ int nve_fused_sequence(const ts_batch *b, ts_neighbor_list *nl, const PairTable 
     a.lang = *lang;
     a.lang_adv = n_steps;
   }
+  // the cells do not change during the loop: their rebuild geometry is computed once
+  static_assert(sizeof(RowGeom) == 14 * sizeof(double), "row geometry record");
+  rc = launch_row_geometry(S, b->cell, a.r_list, reinterpret_cast<RowGeom *>(w.row_geom), st);
+  if (rc != TS_OK) return rc;
+  a.row_geom = reinterpret_cast<const RowGeom *>(w.row_geom);
   // deferred rebuild when the list has its second row buffer: every system starts in buffer 0
   const bool defer = nl->nbr_alt != nullptr;
   if (defer) {

@@ -22,6 +22,14 @@ constexpr int kDeferWgs = 256;      // rebuild workgroups of a step launch with 
 constexpr int kDeferRowsPerWave = 4;  // rows a wavefront of those builds per staging of its system
 constexpr int kDeferSurvCap = 3 * 64;  // survivor queue of a rebuild wavefront (ints)
 
+// Geometry of a cell for the row rebuild: inverse, determinant and reach per lattice direction.
+struct RowGeom {
+  double inv[9];
+  double reach[3];
+  double det;
+  double pad;
+};
+
 struct StepArgs {
   const int64_t *offs;
   const double *pos_in;  // r_n
@@ -70,6 +78,7 @@ struct StepArgs {
   int n_defer_wgs;       // rebuild workgroups at the start of the grid (0: none in this launch)
   int defer_chunks;      // chunks per system of those workgroups
   double pre_factor;     // pre-flag when 2 (|r_{n+1} - ref| + pre_factor |r_{n+1} - r_n|) > skin
+  const RowGeom *row_geom;  // per-system cell geometry of the rebuilds, or null (computed inline)
   // Langevin modes: O step of this launch (step index lang_k of the call) and, with a non-null
   // rng_step, the counter advance by lang_adv done by the call's last launch
   LangParams lang;
@@ -151,6 +160,9 @@ __device__ inline void image_range(double f, double reach, int *lo, int *hi, boo
 }
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st);
+
+// Per-system RowGeom of the cells (cell inverse, determinant, reach at r_list) into out[S].
+int launch_row_geometry(int64_t n_sys, const double *cell, double r_list, RowGeom *out, hipStream_t st);
 
 // Copy back to the list's own buffer the rows of the systems with sel[s] = 1 (deferred rebuild).
 int launch_rows_restore(const StepArgs &a, const int32_t *sel, int64_t n_sys, hipStream_t st);

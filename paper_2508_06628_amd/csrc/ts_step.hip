@@ -377,9 +377,9 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepMidDefer || MODE ==
 
 // Rebuild rows: one wavefront per atom; a workgroup of kRebuildWaves wavefronts handles that many
 // consecutive atoms of one flagged system ("chunks"; chunks_per_sys covers the largest system).
-constexpr int kRebuildWaves = 8;
+constexpr int kRebuildWaves = 4;
 constexpr int kRebuildRowsPerWave = 1;  // rows a wavefront builds per staging of its system
-constexpr int kRebuildGrid = 512;       // workgroups of a rebuild launch (a grid-stride loop over chunks)
+constexpr int kRebuildGrid = 1024;      // workgroups of a rebuild launch (a grid-stride loop over chunks)
 constexpr int kSurvCap = 3 * kWave;  // survivor queue of a wavefront in the wide path
 
 __device__ inline bool shift_ok(int S0, int S1, int S2) {
@@ -387,6 +387,49 @@ __device__ inline bool shift_ok(int S0, int S1, int S2) {
   return ((unsigned)(S0 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT) &
          ((unsigned)(S1 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT) &
          ((unsigned)(S2 + TS_MAX_IMAGE_SHIFT) <= 2u * TS_MAX_IMAGE_SHIFT);
+}
+
+// Cell inverse (row convention: fractional = r inv), determinant and reach_k = r_list / w_k, with
+// w_k = V / |a_{k+1} x a_{k+2}| the perpendicular width, of the cell h (rows are lattice vectors).
+__device__ inline void row_geometry(const double *h, double r_list, RowGeom *g) {
+  const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
+               h22 = h[8];
+  const double det = h00 * (h11 * h22 - h12 * h21) - h01 * (h10 * h22 - h12 * h20) + h02 * (h10 * h21 - h11 * h20);
+  const double id = 1.0 / det;
+  g->inv[0] = (h11 * h22 - h12 * h21) * id;
+  g->inv[1] = (h02 * h21 - h01 * h22) * id;
+  g->inv[2] = (h01 * h12 - h02 * h11) * id;
+  g->inv[3] = (h12 * h20 - h10 * h22) * id;
+  g->inv[4] = (h00 * h22 - h02 * h20) * id;
+  g->inv[5] = (h02 * h10 - h00 * h12) * id;
+  g->inv[6] = (h10 * h21 - h11 * h20) * id;
+  g->inv[7] = (h01 * h20 - h00 * h21) * id;
+  g->inv[8] = (h00 * h11 - h01 * h10) * id;
+  g->det = det;
+  const double vol = fabs(det);
+  const double c0x = h11 * h22 - h12 * h21, c0y = h12 * h20 - h10 * h22, c0z = h10 * h21 - h11 * h20;
+  const double c1x = h21 * h02 - h22 * h01, c1y = h22 * h00 - h20 * h02, c1z = h20 * h01 - h21 * h00;
+  const double c2x = h01 * h12 - h02 * h11, c2y = h02 * h10 - h00 * h12, c2z = h00 * h11 - h01 * h10;
+  g->reach[0] = r_list / (vol / sqrt(c0x * c0x + c0y * c0y + c0z * c0z));
+  g->reach[1] = r_list / (vol / sqrt(c1x * c1x + c1y * c1y + c1z * c1z));
+  g->reach[2] = r_list / (vol / sqrt(c2x * c2x + c2y * c2y + c2z * c2z));
+}
+
+// Per-system geometry of a step loop's rebuilds, once per call (the cells do not change in it).
+__global__ void __launch_bounds__(256) k_row_geometry(int64_t n_sys, const double *__restrict__ cell, double r_list,
+                                                      RowGeom *__restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  RowGeom g;
+  row_geometry(cell + 9 * s, r_list, &g);
+  out[s] = g;
+}
+
+int launch_row_geometry(int64_t n_sys, const double *cell, double r_list, RowGeom *out, hipStream_t st) {
+  if (n_sys <= 0) return TS_OK;
+  hipLaunchKernelGGL(k_row_geometry, dim3((unsigned)ceil_div(n_sys, 256)), dim3(256), 0, st, n_sys, cell, r_list, out);
+  TS_LAUNCH_CHECK();
+  return TS_OK;
 }
 
 // The rows of the systems in list[0 .. *count) from positions a.pos_in, built by workgroup wg of
@@ -425,25 +468,18 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per
       if (threadIdx.x < 9) a.ref_cell[9 * (int64_t)s + threadIdx.x] = h[threadIdx.x];
       if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.status[TS_STATUS_REBUILDS], 1ull);
     }
-    // cell, inverse and reach: uniform values every lane computes itself (no serial section)
+    // cell, inverse and reach: from the step loop's per-call table, else uniform values every lane
+    // computes itself (no serial section); both come from row_geometry
     const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                  h22 = h[8];
-    const double det = h00 * (h11 * h22 - h12 * h21) - h01 * (h10 * h22 - h12 * h20) + h02 * (h10 * h21 - h11 * h20);
-    const double id = 1.0 / det;
-    const double i00 = (h11 * h22 - h12 * h21) * id, i01 = (h02 * h21 - h01 * h22) * id,
-                 i02 = (h01 * h12 - h02 * h11) * id, i10 = (h12 * h20 - h10 * h22) * id,
-                 i11 = (h00 * h22 - h02 * h20) * id, i12 = (h02 * h10 - h00 * h12) * id,
-                 i20 = (h10 * h21 - h11 * h20) * id, i21 = (h01 * h20 - h00 * h21) * id,
-                 i22 = (h00 * h11 - h01 * h10) * id;
-    const double vol = fabs(det);
+    RowGeom geo;
+    if (a.row_geom) geo = a.row_geom[s];
+    else row_geometry(h, a.r_list, &geo);
+    const double i00 = geo.inv[0], i01 = geo.inv[1], i02 = geo.inv[2], i10 = geo.inv[3], i11 = geo.inv[4],
+                 i12 = geo.inv[5], i20 = geo.inv[6], i21 = geo.inv[7], i22 = geo.inv[8];
+    const double det = geo.det;
     if (c0 == 0 && threadIdx.x == 0 && !(isfinite(det) && det != 0.0)) status_raise(a.status, TS_STATUS_NONFINITE, 1);
-    // reach_k = r_list / w_k with w_k = V / |a_{k+1} x a_{k+2}|
-    const double c0x = h11 * h22 - h12 * h21, c0y = h12 * h20 - h10 * h22, c0z = h10 * h21 - h11 * h20;
-    const double c1x = h21 * h02 - h22 * h01, c1y = h22 * h00 - h20 * h02, c1z = h20 * h01 - h21 * h00;
-    const double c2x = h01 * h12 - h02 * h11, c2y = h02 * h10 - h00 * h12, c2z = h00 * h11 - h01 * h10;
-    const double re0 = a.r_list / (vol / sqrt(c0x * c0x + c0y * c0y + c0z * c0z));
-    const double re1 = a.r_list / (vol / sqrt(c1x * c1x + c1y * c1y + c1z * c1z));
-    const double re2 = a.r_list / (vol / sqrt(c2x * c2x + c2y * c2y + c2z * c2z));
+    const double re0 = geo.reach[0], re1 = geo.reach[1], re2 = geo.reach[2];
     // every lattice direction comfortably wider than 2 r_list: at most one image of j is within
     // r_list of i, the nearest one, S = -rint(fractional difference) (a tie at |f + S| = 1/2 is out
     // of reach), and the float32 prefilter on wrapped fractional coordinates below is safe

@@ -1,10 +1,22 @@
 // Host-side validation, parameter tables and status strings.
+#include <atomic>
 #include <cmath>
 #include <limits>
 
 #include "ts_internal.h"
 
 namespace ts {
+
+int device_cus() {
+  static std::atomic<int> cache[64];  // 0: not queried yet
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+  cache[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
 
 int validate_batch(const ts_batch *b, bool need_vel, int64_t *max_atoms) {
   TS_CHECK_ARG(b != nullptr);

@@ -318,8 +318,8 @@ static int fire_iterations(const ts_batch *batch, const ts_fire_state *fs, const
     const bool last = it == n_iter;
     int rc = nl_update(batch, nl, 0, max_atoms, st);
     if (rc != TS_OK) return rc;
-    rc = launch_forces(make_force_args(batch, nl, force, energy, ev ? fa.virial : nullptr, fs->converged), S, tab,
-                       pp->prec, ev, st);
+    rc = launch_forces_batch(batch, nl, tab, pp->prec, force, energy, ev ? fa.virial : nullptr, fs->converged,
+                             max_atoms, st);
     if (rc != TS_OK) return rc;
     rc = pp->prec == TS_PAIR_F32 ? launch_fire_update<float>(fa, cell, last ? 1 : 0, S, max_atoms, part, coef, st)
                                  : launch_fire_update<double>(fa, cell, last ? 1 : 0, S, max_atoms, part, coef, st);

@@ -27,6 +27,11 @@ ForceArgs make_force_args(const ts_batch *b, const ts_neighbor_list *nl, void *f
 // Zero energy/virial of the non-skipped systems (when requested) and launch the force kernel.
 int launch_forces(const ForceArgs &a, int64_t n_sys, const PairTable &t, int prec, bool ev, hipStream_t st);
 
+// Forces (and energy / virial when asked) of the systems whose skip entry is zero (skip may be
+// null): the step loop's workgroup-per-system kernel when max_atoms fits in LDS, else launch_forces.
+int launch_forces_batch(const ts_batch *b, const ts_neighbor_list *nl, const PairTable &t, int prec, void *force,
+                        double *energy, double *virial, const int32_t *skip, int64_t max_atoms, hipStream_t st);
+
 int validate_pair_call(const ts_batch *b, const ts_neighbor_list *nl, const ts_pair_params *pp, int64_t *max_atoms,
                        bool need_vel, bool need_workspace = true);
 

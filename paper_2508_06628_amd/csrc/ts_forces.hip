@@ -179,6 +179,39 @@ int validate_pair_call(const ts_batch *b, const ts_neighbor_list *nl, const ts_p
   return TS_OK;
 }
 
+// Forces (energy and virial when asked) of every system whose skip entry is zero (skip may be
+// null): systems that fit in LDS take the workgroup-per-system kernel of the step loop, larger
+// ones the row-per-atom kernel.  Skipped systems keep their forces, energy and virial.
+int launch_forces_batch(const ts_batch *b, const ts_neighbor_list *nl, const PairTable &t, int prec, void *force,
+                        double *energy, double *virial, const int32_t *skip, int64_t max_atoms, hipStream_t st) {
+  if (max_atoms > kLdsMaxAtoms || b->n_atoms == 0)
+    return launch_forces(make_force_args(b, nl, force, energy, virial, skip), b->n_systems, t, prec,
+                         energy != nullptr || virial != nullptr, st);
+  if (energy || virial) {
+    hipLaunchKernelGGL(k_zero_ev, dim3((unsigned)ceil_div(b->n_systems, 64)), dim3(64), 0, st, b->n_systems, energy,
+                       virial, skip);
+    TS_LAUNCH_CHECK();
+  }
+  StepArgs s;
+  std::memset(&s, 0, sizeof(s));
+  s.offs = b->sys_offsets;
+  s.pos_in = b->pos;
+  s.st_in = stride_of(b);
+  s.st_vel = stride_of(b);
+  s.species = b->species;
+  s.cell = b->cell;
+  s.force = force;
+  s.nbr = reinterpret_cast<uint32_t *>(nl->nbr);
+  s.n_nbr = nl->n_nbr;
+  s.max_nbr = nl->max_nbr;
+  s.epot = energy;
+  s.virial = virial;
+  s.skip = skip;
+  const int mode = (energy || virial) ? kStepForceEV : kStepForce;
+  return launch_step(mode, lanes_for(nl, b->n_atoms), nl->group_atoms, s, t, prec, b->n_systems, max_atoms,
+                     b->h_sys_offsets, st);
+}
+
 }  // namespace ts
 
 extern "C" int ts_pair_forces(const ts_batch *batch, const ts_neighbor_list *nl, const ts_pair_params *pp, void *force,
@@ -187,32 +220,6 @@ extern "C" int ts_pair_forces(const ts_batch *batch, const ts_neighbor_list *nl,
   int rc = ts::validate_pair_call(batch, nl, pp, &max_atoms, false);
   if (rc != TS_OK) return rc;
   TS_CHECK_ARG(force != nullptr);
-  const ts::PairTable t = ts::make_table(pp);
-  if (max_atoms <= ts::kLdsMaxAtoms && batch->n_atoms > 0) {
-    // systems that fit in LDS: the workgroup-per-system kernel the step loop uses, forces only
-    hipStream_t st = ts::as_stream(stream);
-    if (energy && (rc = ts::fill_async<double>(energy, batch->n_systems, 0.0, st)) != TS_OK) return rc;
-    if (virial && (rc = ts::fill_async<double>(virial, 9 * batch->n_systems, 0.0, st)) != TS_OK) return rc;
-    ts::StepArgs s;
-    std::memset(&s, 0, sizeof(s));
-    s.offs = batch->sys_offsets;
-    s.pos_in = batch->pos;
-    s.st_in = ts::stride_of(batch);
-    s.st_vel = ts::stride_of(batch);
-    s.species = batch->species;
-    s.cell = batch->cell;
-    s.force = force;
-    s.nbr = reinterpret_cast<uint32_t *>(nl->nbr);
-    s.n_nbr = nl->n_nbr;
-    s.max_nbr = nl->max_nbr;
-    s.epot = energy;
-    s.virial = virial;
-    const int tl = ts::lanes_for(nl, batch->n_atoms);
-    const int mode = (energy || virial) ? ts::kStepForceEV : ts::kStepForce;
-    return ts::launch_step(mode, tl, nl->group_atoms, s, t, pp->prec, batch->n_systems, max_atoms,
-                           batch->h_sys_offsets, st);
-  }
-  const ts::ForceArgs a = ts::make_force_args(batch, nl, force, energy, virial, nullptr);
-  return ts::launch_forces(a, batch->n_systems, t, pp->prec, energy != nullptr || virial != nullptr,
-                           ts::as_stream(stream));
+  return ts::launch_forces_batch(batch, nl, ts::make_table(pp), pp->prec, force, energy, virial, nullptr, max_atoms,
+                                 ts::as_stream(stream));
 }

@@ -46,6 +46,11 @@ int validate_batch(const ts_batch *b, bool need_vel, int64_t *max_atoms);
 int validate_params(const ts_pair_params *pp);
 int validate_list(const ts_batch *b, const ts_neighbor_list *nl, bool need_workspace = true);
 
+// Compute units of the current device (cached per device; 256 when the query fails) and the LDS
+// of one CU in bytes.
+int device_cus();
+constexpr int64_t kLdsBytes = 160 * 1024;
+
 // ----------------------------------------------------------------------------- list entries
 
 // List entry: j_local in bits 15..31 and each image component S_k + 16 in a 5-bit field, so that the

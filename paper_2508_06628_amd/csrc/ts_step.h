@@ -76,9 +76,10 @@ struct StepArgs {
   int32_t *plist_cur, *plist_next;
   int32_t *pcount_cur, *pcount_next, *pcount_clear;
   int n_defer_wgs;       // rebuild workgroups at the start of the grid (0: none in this launch)
-  int defer_chunks;      // chunks per system of those workgroups
+  int defer_chunks1;     // their chunks per system at one row per wavefront (largest system / 4 waves)
   double pre_factor;     // pre-flag when 2 (|r_{n+1} - ref| + pre_factor |r_{n+1} - r_n|) > skin
   const RowGeom *row_geom;  // per-system cell geometry of the rebuilds, or null (computed inline)
+  const int32_t *skip;      // forces-only modes: systems whose forces, energy and virial stay as they are
   // Langevin modes: O step of this launch (step index lang_k of the call) and, with a non-null
   // rng_step, the counter advance by lang_adv done by the call's last launch
   LangParams lang;

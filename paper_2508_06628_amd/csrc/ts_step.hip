@@ -43,8 +43,8 @@ __device__ inline void preflag_system(const StepArgs &a, int s) {
   }
 }
 
-template <int NW, int RPW, typename Target>
-__device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per_sys, const int32_t *list,
+template <int NW, int RPW, bool COMPACT, typename Target>
+__device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, const int32_t *list,
                              const int32_t *count, Target target);
 
 // The deferred-rebuild modes keep at least four waves per SIMD (at most 128 VGPRs): their rebuild
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepMidDefer || MODE ==
     // deferred rebuild: the systems pre-flagged by the previous launch, from r_n, into the row
     // buffer each of them does not read in this launch (a multiple of kXcds workgroups, so the
     // XCD of every force workgroup below is unchanged)
-    rebuild_rows<kStepThreads / kWave, kDeferRowsPerWave>(a, blockIdx.x, a.n_defer_wgs, a.defer_chunks, a.plist_cur,
+    rebuild_rows<kStepThreads / kWave, kDeferRowsPerWave, false>(a, blockIdx.x, a.n_defer_wgs, a.defer_chunks1, a.plist_cur,
                                                           a.pcount_cur, [&](int q) { return 1 - a.sel_cur[q]; });
     return;
   }
@@ -102,7 +102,9 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepMidDefer || MODE ==
   const int64_t a0 = a.offs[s];
   const int ns = (int)(a.offs[s + 1] - a0);
   const int first = chunk * a.span;
-  if (first >= ns) return;
+  // forces-only modes: the workgroups of a skipped system leave with those past a system's end
+  const bool skipped = (MODE == kStepForce || MODE == kStepForceEV) && a.skip != nullptr && a.skip[s] != 0;
+  if (first >= ns || skipped) return;
   const int end = first + a.span < ns ? first + a.span : ns;  // this chunk's atoms: [first, end)
   const int tid = threadIdx.x;
   const int grp = tid / TL, lane = tid % TL;
@@ -376,10 +378,11 @@ __global__ void __launch_bounds__(kStepThreads, MODE == kStepMidDefer || MODE ==
 }
 
 // Rebuild rows: one wavefront per atom; a workgroup of kRebuildWaves wavefronts handles that many
-// consecutive atoms of one flagged system ("chunks"; chunks_per_sys covers the largest system).
+// consecutive atoms of one flagged system ("chunks"; the chunk count per system covers the largest
+// system).
 constexpr int kRebuildWaves = 4;
-constexpr int kRebuildRowsPerWave = 1;  // rows a wavefront builds per staging of its system
-constexpr int kRebuildGrid = 1024;      // workgroups of a rebuild launch (a grid-stride loop over chunks)
+constexpr int kRebuildWgsPerCu = 4;            // rebuild workgroups a CU holds at most (four waves per SIMD)
+constexpr size_t kRebuildFullLds = 40 * 1024;  // largest LDS use of the full layout (four workgroups per CU)
 constexpr int kSurvCap = 3 * kWave;  // survivor queue of a wavefront in the wide path
 
 __device__ inline bool shift_ok(int S0, int S1, int S2) {
@@ -433,11 +436,14 @@ int launch_row_geometry(int64_t n_sys, const double *cell, double r_list, RowGeo
 }
 
 // The rows of the systems in list[0 .. *count) from positions a.pos_in, built by workgroup wg of
-// n_wg (a grid-stride loop over chunks of NW * RPW consecutive atoms of one system; chunks_per_sys
-// covers the largest system).  Each system's rows, row lengths and reference positions go to the
-// buffer `target(s)` selects (0: nbr, n_nbr, ref_pos; 1: the deferred-rebuild buffers).
-template <int NW, int RPW, typename Target>
-__device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per_sys, const int32_t *list,
+// n_wg (a grid-stride loop over chunks of NW * RPW consecutive atoms of one system; chunks1 =
+// ceil(largest system / NW) is the chunk count per system at one row per wavefront).  Each
+// system's rows, row lengths and reference positions go to the buffer `target(s)` selects (0: nbr,
+// n_nbr, ref_pos; 1: the deferred-rebuild buffers).  COMPACT: for large systems, wide cells keep only the
+// float32 fractional coordinates in LDS (16 B per atom instead of 40) and the exact pass reads the
+// float64 positions of its survivors from memory, so that more workgroups share a CU.
+template <int NW, int RPW, bool COMPACT, typename Target>
+__device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, const int32_t *list,
                              const int32_t *count, Target target) {
   extern __shared__ double lds[];
   // atoms a thread stages: batches of kStageBatch, every load of a batch issued before its stores
@@ -445,6 +451,7 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per
   constexpr int kStage = (kLdsMaxAtoms + kWave * NW - 1) / (kWave * NW);
   // the flagged-system count and this workgroup's first list slot are loaded together (the slot
   // is read speculatively: the list has room for every system)
+  const int chunks_per_sys = (chunks1 + RPW - 1) / RPW;
   const int q0 = wg / chunks_per_sys;
   const int s_spec = q0 < a.n_sys ? list[q0] : 0;
   const int n_cnt = *count;
@@ -486,10 +493,16 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per
     const bool wide = re0 < 0.5 - 1e-3 && re1 < 0.5 - 1e-3 && re2 < 0.5 - 1e-3;
     __syncthreads();  // the previous chunk's readers are done with lds
     // LDS: float64 positions [3][ns]; wide cells also float4 wrapped fractional coordinates [ns]
-    // (16-byte aligned: one padding double when ns is odd) and the wavefronts' survivor queues
+    // (16-byte aligned: one padding double when ns is odd) and the wavefronts' survivor queues.
+    // COMPACT wide cells: the fractional coordinates alone, where the positions would be.
+    constexpr bool kCompact = COMPACT;
+    const bool lds_pos = !(kCompact && wide);  // uniform
     double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
-    float4 *sf = reinterpret_cast<float4 *>(lds + 3 * ns + (ns & 1));
-    int *surv = reinterpret_cast<int *>(sf + ns) + wave * kSurvCap;
+    float4 *sf = reinterpret_cast<float4 *>(kCompact ? lds : lds + 3 * ns + (ns & 1));
+    int *surv = reinterpret_cast<int *>(kCompact ? lds + 3 * ns : reinterpret_cast<double *>(sf + ns)) +
+                wave * kSurvCap;
+    const double *__restrict__ gx = pin + a0, *__restrict__ gy = pin + a.st_in + a0, *__restrict__ gz =
+                                                                                       pin + 2 * a.st_in + a0;
     {
       // the loads of a batch are issued before its stores (past the end a thread reloads the last
       // atom and stores nothing)
@@ -510,9 +523,11 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per
         const int k = threadIdx.x + (u0 + v) * kWave * NW;
         if (k >= ns) break;
         const double x = px[u], y = py[u], z = pz[u];
-        lx[k] = x;
-        ly[k] = y;
-        lz[k] = z;
+        if (lds_pos) {
+          lx[k] = x;
+          ly[k] = y;
+          lz[k] = z;
+        }
         if (wide) {
           const double f0 = x * i00 + y * i10 + z * i20, f1 = x * i01 + y * i11 + z * i21,
                        f2 = x * i02 + y * i12 + z * i22;
@@ -528,7 +543,7 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per
     const int li = c0 + wave + NW * rr;
     if (li >= ns) break;  // uniform over the wavefront; no block barrier follows before the loop top
     const int64_t i = a0 + li;
-    const double rx = lx[li], ry = ly[li], rz = lz[li];
+    const double rx = lds_pos ? lx[li] : gx[li], ry = lds_pos ? ly[li] : gy[li], rz = lds_pos ? lz[li] : gz[li];
     int cnt = 0;
     bool shift_bad = false;
     if (wide) {
@@ -549,7 +564,8 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per
       auto exact = [&](int n) {  // the first n queued survivors
         __builtin_amdgcn_wave_barrier();  // queue writes of other lanes before these reads
         const int j = lane < n ? surv[lane] : li;
-        const double drx = lx[j] - rx, dry = ly[j] - ry, drz = lz[j] - rz;
+        const double drx = (lds_pos ? lx[j] : gx[j]) - rx, dry = (lds_pos ? ly[j] : gy[j]) - ry,
+                     drz = (lds_pos ? lz[j] : gz[j]) - rz;
         const double f0 = drx * i00 + dry * i10 + drz * i20, f1 = drx * i01 + dry * i11 + drz * i21,
                      f2 = drx * i02 + dry * i12 + drz * i22;
         // nearest integers without rounding or conversion instructions: t = f + 1.5 2^52 rounds f to
@@ -715,21 +731,34 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks_per
 
 // Rows of the systems flagged for a rebuild before the next step (the list's own buffer of each
 // system: the one the step kernel reads next).
-__global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs a, int chunks_per_sys) {
-  rebuild_rows<kRebuildWaves, kRebuildRowsPerWave>(a, blockIdx.x, gridDim.x, chunks_per_sys, a.list_cur, a.count_cur,
-                                                   [&](int s) { return a.sel_cur ? a.sel_cur[s] : 0; });
+template <bool COMPACT>
+__global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs a, int chunks1) {
+  rebuild_rows<kRebuildWaves, 1, COMPACT>(a, blockIdx.x, gridDim.x, chunks1, a.list_cur, a.count_cur,
+                                          [&](int s) { return a.sel_cur ? a.sel_cur[s] : 0; });
 }
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st) {
-  const int chunks = (int)ceil_div(max_atoms, kRebuildWaves * kRebuildRowsPerWave);
-  const int64_t work = n_sys * chunks;
-  const unsigned grid = (unsigned)(work < kRebuildGrid ? work : kRebuildGrid);
   // float64 positions, float4 fractional coordinates (after one alignment double) and the
-  // survivor queues (wide cells)
-  const size_t shm = (size_t)(5 * max_atoms + 1) * sizeof(double) + sizeof(int) * kSurvCap * kRebuildWaves;
+  // survivor queues (wide cells); beyond kRebuildFullLds, the compact layout (float64 positions of
+  // cells that are not wide, else the fractional coordinates alone)
+  const size_t queues = sizeof(int) * kSurvCap * kRebuildWaves;
+  const size_t full = (size_t)(5 * max_atoms + 1) * sizeof(double) + queues;
   StepArgs b = a;
   b.n_sys = (int)n_sys;
-  hipLaunchKernelGGL(k_rebuild_rows, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, b, chunks);
+  const bool compact = full > kRebuildFullLds;
+  const size_t shm = compact ? (size_t)3 * max_atoms * sizeof(double) + queues : full;
+  // one workgroup per chunk up to what the CUs hold at once (every workgroup then loops over chunks
+  // from the start, none waits for a free slot)
+  const int chunks1 = (int)ceil_div(max_atoms, kRebuildWaves);
+  const int64_t work = n_sys * chunks1;
+  const int64_t fit = kLdsBytes / (int64_t)shm;
+  const int64_t per_cu = fit < kRebuildWgsPerCu ? fit : kRebuildWgsPerCu;
+  const int64_t resident = (int64_t)device_cus() * (per_cu > 0 ? per_cu : 1);
+  const unsigned grid = (unsigned)(work < resident ? work : resident);
+  if (compact)
+    hipLaunchKernelGGL(k_rebuild_rows<true>, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, b, chunks1);
+  else
+    hipLaunchKernelGGL(k_rebuild_rows<false>, dim3(grid), dim3(kWave * kRebuildWaves), shm, st, b, chunks1);
   TS_LAUNCH_CHECK();
   return TS_OK;
 }
@@ -793,7 +822,7 @@ int launch_step(int mode, int tl, int group_atoms, StepArgs a, const PairTable &
   size_t shm = (size_t)3 * sizeof(double) * (size_t)max_atoms;
   if (a.n_defer_wgs > 0) {
     constexpr int nw = kStepThreads / kWave;
-    a.defer_chunks = (int)ceil_div(max_atoms, nw * kDeferRowsPerWave);
+    a.defer_chunks1 = (int)ceil_div(max_atoms, nw);
     const size_t shm_rb = (size_t)(5 * max_atoms + 1) * sizeof(double) + sizeof(int) * kSurvCap * nw;
     shm = shm_rb > shm ? shm_rb : shm;
   }

@@ -292,11 +292,13 @@ def _check_list(nl, what):
 
 def fire_copper(api, torch, max_iter=20000, skin=1.0):
     """Batched FIRE of positions and cell on the uneven 512-system Morse copper batch until every
-    system has max |F| < fmax (and the cell force too): repeated ts_fire_step calls, each one
-    persistent launch (largest system first, a converged system frees its workgroup) plus a bounded
-    tail of per-iteration launches; the host reads the convergence flags between calls.  The list
-    skin is a tuning parameter of the relaxation (forces do not depend on it): 1 A trades longer
-    rows for fewer rebuilds under cell changes."""
+    system has max |F| < fmax (and the cell force too): repeated ts_fire_step calls on the path the
+    autotuner picks (one persistent launch per call, largest system first, plus a bounded tail of
+    per-iteration launches; or per-iteration launches throughout) and its lanes per atom; the host
+    reads the convergence flags between calls.  The list skin is a tuning parameter of the
+    relaxation (forces do not depend on it): 1 A trades longer rows for fewer rebuilds under cell
+    changes."""
+    from paper_2508_06628_amd.autotune import tune_fire
     from workloads import copper_uneven_batch
     w = copper_uneven_batch(512, seed=2)
     pot = w.potential
@@ -307,11 +309,13 @@ def fire_copper(api, torch, max_iter=20000, skin=1.0):
     cfgd["relax_cell"] = True
     cfgd["max_iter"] = max_iter
     cfg = api.fire_config(**cfgd)
+    tune = tune_fire(b, nl, pp, cfg)
+    log(f"FIRE autotune: {tune}")
     fs = api.FireState(b, cfg)
     F = api.force_buffer(b, w.pair_prec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    calls = api.fire_relax(b, fs, cfg, nl, pp, F)
+    calls = api.fire_relax(b, fs, cfg, nl, pp, F, persistent=tune["persistent"])
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     st = _check_list(nl, "copper FIRE")
@@ -321,7 +325,8 @@ def fire_copper(api, torch, max_iter=20000, skin=1.0):
                 seconds=round(sec, 4), calls=calls,
                 converged=int(fs.converged.sum().item()), n_systems=w.n_systems, iterations_mean=round(float(it.mean()), 1),
                 iterations_max=int(it.max()), value=round(work / sec, 1), unit="atom-iterations/s",
-                list_rebuilds=int(st[2]), list_max_nbr=int(st[0]), list_capacity=nl.max_nbr)
+                list_rebuilds=int(st[2]), list_max_nbr=int(st[0]), list_capacity=nl.max_nbr,
+                persistent=tune["persistent"], lanes_per_atom=tune["lanes_per_atom"], tune_ms=tune.get("ms"))
 
 
 def copper_force_roofline(api, torch, reps=50):

@@ -1,4 +1,4 @@
-"""Launch-shape autotuner for the batched NVE step loop.
+"""Launch-shape autotuner for the batched NVE step loop and the FIRE relaxation.
 
 The fused step kernel spreads each atom's neighbor row over ``lanes_per_atom`` lanes of a
 wavefront (1, 2, 4 or 8), and a workgroup owns ``group_atoms`` atoms of one system (one or more
@@ -9,6 +9,11 @@ short graph replay of the real workload for every candidate on a scratch copy of
 returns the fastest; results are cached on disk per (device architecture, potential, precision, size bucket)
 so later runs skip the sweep.  Only timing is done here: every candidate runs the same kernels
 through the C ABI and computes the same trajectory up to float64 summation order.
+
+``tune_fire`` picks how ``ts_fire_step`` runs a relaxation: one persistent launch per call (each
+system on one workgroup, converged systems freeing theirs) or the per-iteration kernels (every
+open system spread over many workgroups), and the lanes per atom of the force kernel.  Batches
+of many small systems favour the first, batches with large systems the second.
 """
 from __future__ import annotations
 
@@ -110,3 +115,46 @@ def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float
 def tuned_lanes(batch, nl, pp) -> Optional[int]:
     e = _load().get(key(batch, nl, pp))
     return None if e is None else int(e["lanes_per_atom"])
+
+
+FIRE_LANE_CHOICES = (2, 4)
+
+
+def tune_fire(batch: api.Batch, nl: api.NeighborList, pp, cfg, iters: int = 32, use_cache: bool = True,
+              choices=FIRE_LANE_CHOICES) -> dict:
+    """Pick the FIRE path (persistent launch or per-iteration kernels) and lanes_per_atom for
+    ``ts_fire_step`` on this workload.  Each candidate relaxes a scratch copy of the batch from a
+    fresh FIRE state for ``iters`` iterations (after two warm-up iterations).  Returns
+    {"persistent": P, "lanes_per_atom": L, "ms": {"P/L": t, ...}, "cached": bool} and sets the lanes
+    on ``nl``."""
+    k = f"fire/{key(batch, nl, pp)}/cell{int(cfg.relax_cell)}"
+    cache = _load() if use_cache else {}
+    if k in cache:
+        nl.lanes_per_atom = int(cache[k]["lanes_per_atom"])
+        return dict(cache[k], cached=True)
+    prec = "f32" if pp.prec == 0 else "f64"
+    timings = {}
+    for persistent in (True, False):
+        for lanes in choices:
+            b = batch.clone()
+            trial = api.NeighborList(b, nl.cutoff, nl.skin, nl.max_nbr, nl.bin_factor, nl.half, lanes, nl.group_atoms)
+            api.ts_neighbor_build(b, trial, force=True)
+            fs = api.FireState(b, cfg)
+            F = api.force_buffer(b, prec)
+            api.ts_fire_step(b, fs, cfg, trial, pp, 2, F, persistent=persistent)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            api.ts_fire_step(b, fs, cfg, trial, pp, iters, F, persistent=persistent)
+            e1.record()
+            torch.cuda.synchronize()
+            timings[(persistent, lanes)] = round(e0.elapsed_time(e1), 3)
+            del trial, b, F, fs
+    persistent, lanes = min(timings, key=timings.get)
+    entry = {"persistent": bool(persistent), "lanes_per_atom": int(lanes),
+             "ms": {f"{int(p2)}/{l2}": v for (p2, l2), v in timings.items()}}
+    if use_cache:
+        cache[k] = entry
+        _store(cache)
+    nl.lanes_per_atom = int(lanes)
+    return dict(entry, cached=False)

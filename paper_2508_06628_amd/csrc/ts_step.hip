@@ -492,11 +492,12 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
     // of reach), and the float32 prefilter on wrapped fractional coordinates below is safe
     const bool wide = re0 < 0.5 - 1e-3 && re1 < 0.5 - 1e-3 && re2 < 0.5 - 1e-3;
     __syncthreads();  // the previous chunk's readers are done with lds
-    // LDS: float64 positions [3][ns]; wide cells also float4 wrapped fractional coordinates [ns]
-    // (16-byte aligned: one padding double when ns is odd) and the wavefronts' survivor queues.
-    // COMPACT wide cells: the fractional coordinates alone, where the positions would be.
+    // LDS: float64 positions [3][ns], float4 wrapped fractional coordinates [ns] (16-byte aligned:
+    // one padding double when ns is odd) and the wavefronts' survivor queues.  COMPACT: the
+    // fractional coordinates alone, where the positions would be (the exact passes read float64
+    // positions from memory).
     constexpr bool kCompact = COMPACT;
-    const bool lds_pos = !(kCompact && wide);  // uniform
+    constexpr bool lds_pos = !kCompact;
     double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
     float4 *sf = reinterpret_cast<float4 *>(kCompact ? lds : lds + 3 * ns + (ns & 1));
     int *surv = reinterpret_cast<int *>(kCompact ? lds + 3 * ns : reinterpret_cast<double *>(sf + ns)) +
@@ -528,7 +529,7 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
           ly[k] = y;
           lz[k] = z;
         }
-        if (wide) {
+        if (kCompact || wide) {  // the small-system kernel scans the other cells exhaustively
           const double f0 = x * i00 + y * i10 + z * i20, f1 = x * i01 + y * i11 + z * i21,
                        f2 = x * i02 + y * i12 + z * i22;
           sf[k] = make_float4((float)(f0 - floor(f0)), (float)(f1 - floor(f1)), (float)(f2 - floor(f2)), 0.0f);
@@ -546,21 +547,59 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
     const double rx = lds_pos ? lx[li] : gx[li], ry = lds_pos ? ly[li] : gy[li], rz = lds_pos ? lz[li] : gz[li];
     int cnt = 0;
     bool shift_bad = false;
-    if (wide) {
-      // Pass 1, float32: the nearest-image distance from wrapped fractional coordinates.  A candidate
-      // survives below r_list + delta, where delta bounds the float32 rounding of the fractional
-      // coordinates and of the distance (a few 1e-5 A at most) with a wide margin, so every pair
-      // within r_list survives.  Survivors are queued in j order.
-      // Pass 2, float64: each batch of up to 64 survivors takes the exact test of the general path
-      // (same pair vector arithmetic) and is compacted into the row in queue order.
-      const float4 fi = sf[li];
-      const float g00 = (float)h00, g01 = (float)h01, g02 = (float)h02, g10 = (float)h10, g11 = (float)h11,
-                  g12 = (float)h12, g20 = (float)h20, g21 = (float)h21, g22 = (float)h22;
+    // Pass 1, float32 on wrapped fractional coordinates: candidates are queued (in j order) when
+    // they may have an image within r_list.  Pass 2, float64: each batch of up to 64 queued
+    // candidates takes the exact test and is compacted into the row in queue order.  The float32
+    // tests use r_list + delta, where delta bounds their rounding (a few 1e-5 A at most) with a wide
+    // margin, so no pair within r_list is lost.
+    //  * wide cells (every direction wider than 2 r_list): at most one image of j is within r_list
+    //    of i, the nearest one, S = -rint(fractional difference) (a tie at |f + S| = 1/2 is out of
+    //    reach); pass 1 is the nearest-image distance and pass 2 tests that image;
+    //  * other cells, large systems (COMPACT): any image's distance is at least |d_k| w_k in every
+    //    direction k (d the nearest-image fractional difference, w_k the width across the planes of
+    //    the other two lattice vectors); pass 1 keeps candidates with max_k |d_k| w_k below the
+    //    bound and pass 2 enumerates every image within reach;
+    //  * other cells, small systems: every candidate takes pass 2.
+    auto bound = [&]() {  // r_list + delta
       const double rowsum = sqrt(h00 * h00 + h01 * h01 + h02 * h02) + sqrt(h10 * h10 + h11 * h11 + h12 * h12) +
                             sqrt(h20 * h20 + h21 * h21 + h22 * h22);
-      const double rc = a.r_list + 1e-4 + 4e-6 * rowsum;
+      return a.r_list + 1e-4 + 4e-6 * rowsum;
+    };
+    int pend = 0;
+    // queue the survivors of two blocks of 64 candidates per iteration (independent chains until
+    // their ballots); the queue holds up to 3 x 64 survivors, and every full 64 of them take pass 2
+    auto scan = [&](auto pass1, auto pass2) {
+      for (int j0 = 0; j0 < ns; j0 += 2 * kWave) {
+        const int ja = j0 + lane, jb = j0 + kWave + lane;
+        const bool pa = pass1(ja), pb = pass1(jb);
+        const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+        const int qa = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0));
+        if (pa) surv[qa] = ja;
+        pend += __popcll(ma);
+        const int qb = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0));
+        if (pb) surv[qb] = jb;
+        pend += __popcll(mb);
+        while (pend >= kWave) {
+          pass2(kWave);
+          // move the overflow (fewer than 2 x 64 entries) to the front of the queue
+          const int rest = pend - kWave;
+          const int m0 = lane < rest ? surv[kWave + lane] : 0;
+          const int m1 = lane + kWave < rest ? surv[2 * kWave + lane] : 0;
+          __builtin_amdgcn_wave_barrier();
+          if (lane < rest) surv[lane] = m0;
+          if (lane + kWave < rest) surv[kWave + lane] = m1;
+          __builtin_amdgcn_wave_barrier();
+          pend = rest;
+        }
+      }
+      if (pend > 0) pass2(pend);
+    };
+    if (wide) {
+      const float4 fi = sf[li];
+      const double rc = bound();
+      const float g00 = (float)h00, g01 = (float)h01, g02 = (float)h02, g10 = (float)h10, g11 = (float)h11,
+                  g12 = (float)h12, g20 = (float)h20, g21 = (float)h21, g22 = (float)h22;
       const float rc2f = (float)(rc * rc);
-      int pend = 0;
       auto exact = [&](int n) {  // the first n queued survivors
         __builtin_amdgcn_wave_barrier();  // queue writes of other lanes before these reads
         const int j = lane < n ? surv[lane] : li;
@@ -600,64 +639,80 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
         const float dz = dfx * g02 + dfy * g12 + dfz * g22;
         return (j < ns) & (dx * dx + dy * dy + dz * dz < rc2f);
       };
-      // two blocks of 64 candidates per iteration (independent chains until their ballots); the
-      // queue holds up to 3 x 64 survivors, and every full 64 of them take the exact pass
-      for (int j0 = 0; j0 < ns; j0 += 2 * kWave) {
-        const int ja = j0 + lane, jb = j0 + kWave + lane;
-        const bool pa = near_f32(ja), pb = near_f32(jb);
-        const uint64_t ma = __ballot(pa), mb = __ballot(pb);
-        const int qa = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0));
-        if (pa) surv[qa] = ja;
-        pend += __popcll(ma);
-        const int qb = pend + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0));
-        if (pb) surv[qb] = jb;
-        pend += __popcll(mb);
-        while (pend >= kWave) {
-          exact(kWave);
-          // move the overflow (fewer than 2 x 64 entries) to the front of the queue
-          const int rest = pend - kWave;
-          const int m0 = lane < rest ? surv[kWave + lane] : 0;
-          const int m1 = lane + kWave < rest ? surv[2 * kWave + lane] : 0;
-          __builtin_amdgcn_wave_barrier();
-          if (lane < rest) surv[lane] = m0;
-          if (lane + kWave < rest) surv[kWave + lane] = m1;
-          __builtin_amdgcn_wave_barrier();
-          pend = rest;
-        }
-      }
-      if (pend > 0) exact(pend);
-    }
-    for (int j0 = 0; j0 < (wide ? 0 : ns); j0 += kWave) {
-      const int j = j0 + lane;
-      int c = 0;
-      uint32_t e1 = 0;
-      int lo0 = 0, hi0 = -1, lo1 = 0, hi1 = -1, lo2 = 0, hi2 = -1;
-      double drx = 0.0, dry = 0.0, drz = 0.0;
-      if (j < ns) {
-        drx = lx[j] - rx;
-        dry = ly[j] - ry;
-        drz = lz[j] - rz;
-        image_range(drx * i00 + dry * i10 + drz * i20, re0, &lo0, &hi0, &shift_bad);
-        image_range(drx * i01 + dry * i11 + drz * i21, re1, &lo1, &hi1, &shift_bad);
-        image_range(drx * i02 + dry * i12 + drz * i22, re2, &lo2, &hi2, &shift_bad);
-        if (lo0 == hi0 && lo1 == hi1 && lo2 == hi2) {
-          // one candidate image (always the case when the cell is wider than 2 r_list)
-          const int S0 = lo0, S1 = lo1, S2 = lo2;
-          if (!(j == li && S0 == 0 && S1 == 0 && S2 == 0)) {
-            const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
-            const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
-            const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
-            const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
-            if (norm2(dx, dy, dz) < rl2 && (!a.half || li < j || (li == j && fs > 0))) {
-              if (shift_ok(S0, S1, S2)) {
-                e1 = pack_entry(j, S0, S1, S2);
-                c = 1;
-              } else {
-                shift_bad = true;
+      scan(near_f32, exact);
+    } else {
+      // every image within r_list of candidate j (one per lane, valid lanes only), compacted into
+      // the row in (lane, S0, S1, S2) order
+      auto multi = [&](int j, bool valid) {
+        int c = 0;
+        uint32_t e1 = 0;
+        int lo0 = 0, hi0 = -1, lo1 = 0, hi1 = -1, lo2 = 0, hi2 = -1;
+        double drx = 0.0, dry = 0.0, drz = 0.0;
+        if (valid) {
+          drx = (lds_pos ? lx[j] : gx[j]) - rx;
+          dry = (lds_pos ? ly[j] : gy[j]) - ry;
+          drz = (lds_pos ? lz[j] : gz[j]) - rz;
+          image_range(drx * i00 + dry * i10 + drz * i20, re0, &lo0, &hi0, &shift_bad);
+          image_range(drx * i01 + dry * i11 + drz * i21, re1, &lo1, &hi1, &shift_bad);
+          image_range(drx * i02 + dry * i12 + drz * i22, re2, &lo2, &hi2, &shift_bad);
+          if (lo0 == hi0 && lo1 == hi1 && lo2 == hi2) {
+            // one candidate image (always the case when the cell is wider than 2 r_list)
+            const int S0 = lo0, S1 = lo1, S2 = lo2;
+            if (!(j == li && S0 == 0 && S1 == 0 && S2 == 0)) {
+              const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+              const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+              const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+              const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
+              if (norm2(dx, dy, dz) < rl2 && (!a.half || li < j || (li == j && fs > 0))) {
+                if (shift_ok(S0, S1, S2)) {
+                  e1 = pack_entry(j, S0, S1, S2);
+                  c = 1;
+                } else {
+                  shift_bad = true;
+                }
               }
             }
+          } else {
+            for (int S0 = lo0; S0 <= hi0; ++S0)
+              for (int S1 = lo1; S1 <= hi1; ++S1)
+                for (int S2 = lo2; S2 <= hi2; ++S2) {
+                  if (j == li && S0 == 0 && S1 == 0 && S2 == 0) continue;
+                  const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
+                  const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
+                  const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
+                  if (!(norm2(dx, dy, dz) < rl2)) continue;
+                  const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
+                  if (a.half && !(li < j || (li == j && fs > 0))) continue;
+                  if (!shift_ok(S0, S1, S2)) {
+                    shift_bad = true;
+                    continue;
+                  }
+                  if (c == 0) e1 = pack_entry(j, S0, S1, S2);
+                  ++c;
+                }
           }
+        }
+        // exclusive prefix of the per-lane counts across the wavefront (ballot + mbcnt when every
+        // lane holds at most one entry)
+        int pre, total;
+        if (__ballot(c > 1) == 0) {
+          const uint64_t one = __ballot(c == 1);
+          pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(one >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)one, 0));
+          total = __popcll(one);
         } else {
+          int incl = c;
+#pragma unroll
+          for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += t;
+          }
+          pre = incl - c;
+          total = __shfl(incl, kWave - 1, kWave);
+        }
+        int pos = cnt + pre;
+        if (c == 1) {
+          if (pos < a.max_nbr) nbr[row_index(pos, i, st)] = e1;
+        } else if (c > 1) {
           for (int S0 = lo0; S0 <= hi0; ++S0)
             for (int S1 = lo1; S1 <= hi1; ++S1)
               for (int S2 = lo2; S2 <= hi2; ++S2) {
@@ -668,52 +723,39 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
                 if (!(norm2(dx, dy, dz) < rl2)) continue;
                 const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
                 if (a.half && !(li < j || (li == j && fs > 0))) continue;
-                if (!shift_ok(S0, S1, S2)) {
-                  shift_bad = true;
-                  continue;
-                }
-                if (c == 0) e1 = pack_entry(j, S0, S1, S2);
-                ++c;
+                if (!shift_ok(S0, S1, S2)) continue;
+                if (pos < a.max_nbr) nbr[row_index(pos, i, st)] = pack_entry(j, S0, S1, S2);
+                ++pos;
               }
         }
-      }
-      // exclusive prefix of the per-lane counts across the wavefront (ballot + mbcnt when every
-      // lane holds at most one entry)
-      int pre, total;
-      if (__ballot(c > 1) == 0) {
-        const uint64_t one = __ballot(c == 1);
-        pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(one >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)one, 0));
-        total = __popcll(one);
+        cnt += total;
+      };
+      if constexpr (COMPACT) {
+        const float4 fi = sf[li];
+        const double rc = bound();
+        // perpendicular widths w_k = r_list / reach_k
+        const float w0 = (float)(a.r_list / re0), w1 = (float)(a.r_list / re1), w2 = (float)(a.r_list / re2);
+        const float rcf = (float)rc;
+        auto slab_f32 = [&](int j) {  // float32 slab test of candidate j (false past the end)
+          const float4 fj = sf[j < ns ? j : li];
+          float d0 = fj.x - fi.x, d1 = fj.y - fi.y, d2 = fj.z - fi.z;
+          d0 -= rintf(d0);
+          d1 -= rintf(d1);
+          d2 -= rintf(d2);
+          const float m = fmaxf(fabsf(d0) * w0, fmaxf(fabsf(d1) * w1, fabsf(d2) * w2));
+          return (j < ns) & (m < rcf);
+        };
+        // the first n queued candidates
+        auto images = [&](int n) {
+          __builtin_amdgcn_wave_barrier();  // queue writes of other lanes before these reads
+          multi(lane < n ? surv[lane] : li, lane < n);
+        };
+        scan(slab_f32, images);
       } else {
-        int incl = c;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-          const int t = __shfl_up(incl, o, kWave);
-          if (lane >= o) incl += t;
-        }
-        pre = incl - c;
-        total = __shfl(incl, kWave - 1, kWave);
+        // small systems: every candidate takes the exact test (the shorter code keeps the latency
+        // of the step loops' rebuild low)
+        for (int j0 = 0; j0 < ns; j0 += kWave) multi(j0 + lane, j0 + lane < ns);
       }
-      int pos = cnt + pre;
-      if (c == 1) {
-        if (pos < a.max_nbr) nbr[row_index(pos, i, st)] = e1;
-      } else if (c > 1) {
-        for (int S0 = lo0; S0 <= hi0; ++S0)
-          for (int S1 = lo1; S1 <= hi1; ++S1)
-            for (int S2 = lo2; S2 <= hi2; ++S2) {
-              if (j == li && S0 == 0 && S1 == 0 && S2 == 0) continue;
-              const double dx = shift_comp(drx, S0, S1, S2, h00, h10, h20);
-              const double dy = shift_comp(dry, S0, S1, S2, h01, h11, h21);
-              const double dz = shift_comp(drz, S0, S1, S2, h02, h12, h22);
-              if (!(norm2(dx, dy, dz) < rl2)) continue;
-              const int fs = S0 != 0 ? S0 : (S1 != 0 ? S1 : S2);
-              if (a.half && !(li < j || (li == j && fs > 0))) continue;
-              if (!shift_ok(S0, S1, S2)) continue;
-              if (pos < a.max_nbr) nbr[row_index(pos, i, st)] = pack_entry(j, S0, S1, S2);
-              ++pos;
-            }
-      }
-      cnt += total;
     }
     if (lane == 0) {
       n_nbr[i] = cnt < a.max_nbr ? cnt : a.max_nbr;

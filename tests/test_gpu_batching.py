@@ -283,6 +283,41 @@ def test_cell_list_narrow_triclinic_unwrapped(bin_factor, half):
     assert nl.read_status()[2] == 1
 
 
+@pytest.mark.parametrize("narrow,half", [(4.2, False), (4.2, True), (2.5, False)])
+def test_row_rebuild_large_narrow_triclinic(narrow, half):
+    """Systems of 1200-2048 atoms take the row rebuild's large-system kernel (fractional coordinates
+    alone in LDS); their sheared cells are narrower than 2 r_list along one direction (2.5: narrower
+    than r_list itself, three images of one pair), so the slab prefilter and the multi-image exact
+    pass build the rows.  Sampled rows must equal the oracle's pair sets, in canonical order."""
+    api = _api()
+    w = narrow_triclinic_batch(60 + int(10 * narrow) + int(half), n_systems=2, n_range=(1200, 2048), narrow=narrow,
+                               empty_first=True)
+    r_list = 2.8
+    b = api.Batch.from_workload(w)
+    assert 947 < b.max_system_atoms <= 2048
+    nl = api.build_neighbor_list(b, 2.5, 0.3, bin_factor=2, half=half)
+    st = nl.read_status()
+    assert st[1] == 0 and st[3] == 0 and st[4] == 0
+    i_all, j_all, s0, s1, s2 = nl.entries()
+    rng = np.random.default_rng(int(10 * narrow))
+    for s in range(1, w.n_systems):
+        sl = w.system(s)
+        n = sl.stop - sl.start
+        rows = np.sort(rng.choice(n, size=32, replace=False))
+        o = opairs.system_pairs(w.pos[sl], w.cell[s], r_list, rows=rows, half=half)
+        sel = np.isin(i_all, sl.start + rows)
+        g = dict(i=i_all[sel] - sl.start, j=j_all[sel], S=np.stack([s0[sel], s1[sel], s2[sel]], 1))
+        d = w.pos[sl][g["j"]] - w.pos[sl][g["i"]] + g["S"] @ w.cell[s]
+        g["r2"] = (d * d).sum(1)
+        kg, ko = opairs.pair_keys(g, r_list, 1e-9), opairs.pair_keys(o, r_list, 1e-9)
+        assert kg.shape == ko.shape and np.array_equal(kg, ko), s
+        assert np.unique(ko[:, 1:3], axis=0).shape[0] < ko.shape[0]  # several images of one pair
+        for r in rows[:8]:
+            m = i_all == sl.start + r
+            row = np.stack([j_all[m], s0[m], s1[m], s2[m]], 1)
+            assert np.array_equal(row, row[np.lexsort(row.T[::-1])])
+
+
 # ----------------------------------------------------------------------------- overflow recovery
 
 

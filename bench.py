@@ -496,9 +496,10 @@ def profile_kernels(api, torch, w, lanes, bin_factor, reps=20, copy_mib=256, gro
                 list_entries=int(nl.n_nbr.sum().item()), copy_bytes_each_way=n * 4, copy_launches=3)
 
 
-def profile_copper(api, torch, reps=20, copy_mib=256):
+def profile_copper(api, torch, reps=20, rebuilds=10, copy_mib=256):
     """Fixed launch sequence for rocprofv3 runs on the uneven 512-system copper batch: the pair-force
-    kernel ``reps`` times (its 290 MB list is beyond the Infinity Cache) and the calibration copy."""
+    kernel ``reps`` times (its 290 MB list is beyond the Infinity Cache), ``rebuilds`` forced rebuilds
+    of every row (the large-system row rebuild) and the calibration copy."""
     from workloads import copper_uneven_batch
     w = copper_uneven_batch(512, seed=2)
     b = api.Batch.from_workload(w)
@@ -507,6 +508,8 @@ def profile_copper(api, torch, reps=20, copy_mib=256):
     F = api.force_buffer(b, w.pair_prec)
     for _ in range(reps):
         api.ts_pair_forces(b, nl, pp, F)
+    for _ in range(rebuilds):
+        api.ts_neighbor_build(b, nl, force=True)
     n = copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -515,8 +518,10 @@ def profile_copper(api, torch, reps=20, copy_mib=256):
     torch.cuda.synchronize()
     entries = int(nl.n_nbr.sum().item())
     alg = b.n_atoms * (24 + 4 + 12) + 4 * entries + w.n_systems * (8 + 72)
+    counts = np.diff(b.h_offsets).astype(np.float64)
     return dict(mode="profile", workload="copper_morse_forces_512_uneven", n_atoms=b.n_atoms, force_launches=reps,
-                list_entries=entries, alg_bytes_per_launch=alg, copy_bytes_each_way=n * 4, copy_launches=3)
+                list_entries=entries, alg_bytes_per_launch=alg, rebuild_launches=rebuilds,
+                rebuild_candidate_pairs=int((counts ** 2).sum()), copy_bytes_each_way=n * 4, copy_launches=3)
 
 
 def main():

@@ -377,14 +377,20 @@ NlWork nl_work(void *ws, int64_t n_atoms, int64_t n_sys) {
   return w;
 }
 
-// Rebuild list of the small-system path: with force every system, else none yet (flags cleared).
+// Rebuild list of the small-system path: with force every system, else none yet (flags cleared);
+// and each system's cell geometry for the row rebuild (one thread per system).
 __global__ void __launch_bounds__(256) k_list_init(int64_t n_sys, int force, int32_t *__restrict__ flags,
-                                                   int32_t *__restrict__ list, int32_t *__restrict__ count) {
-  for (int64_t s = threadIdx.x; s < n_sys; s += blockDim.x) {
-    flags[s] = 0;
-    if (force) list[s] = (int32_t)s;
-  }
-  if (threadIdx.x == 0) *count = force ? (int32_t)n_sys : 0;
+                                                   int32_t *__restrict__ list, int32_t *__restrict__ count,
+                                                   const double *__restrict__ cell, double r_list,
+                                                   RowGeom *__restrict__ geom) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) *count = force ? (int32_t)n_sys : 0;
+  if (s >= n_sys) return;
+  flags[s] = 0;
+  if (force) list[s] = (int32_t)s;
+  RowGeom g;
+  row_geometry(cell + 9 * s, r_list, &g);
+  geom[s] = g;
 }
 
 // Validity test of every atom; the first atom of a system to exceed the bound appends the system to
@@ -414,7 +420,9 @@ int nl_update(const ts_batch *b, ts_neighbor_list *nl, int force, int64_t max_at
     // systems that fit in LDS: a device list of the systems to rebuild and the row kernel of the
     // fused step loop (canonical rows straight from a wavefront scan, no sort)
     int32_t *list = w.flags3 + 3 * S, *count = w.flags3 + 6 * S + 4;
-    hipLaunchKernelGGL(k_list_init, dim3(1), dim3(256), 0, st, S, force, w.flags, list, count);
+    RowGeom *geom = reinterpret_cast<RowGeom *>(w.row_geom);
+    hipLaunchKernelGGL(k_list_init, dim3((unsigned)ceil_div(S > 0 ? S : 1, 256)), dim3(256), 0, st, S, force, w.flags,
+                       list, count, b->cell, r_list, geom);
     TS_LAUNCH_CHECK();
     if (n == 0) return TS_OK;
     if (!force) {
@@ -440,6 +448,7 @@ int nl_update(const ts_batch *b, ts_neighbor_list *nl, int force, int64_t max_at
     a.skin = nl->skin;
     a.list_cur = list;
     a.count_cur = count;
+    a.row_geom = geom;
     return launch_rebuild(a, S, max_atoms, st);
   }
   if (!force && n > 0) {

@@ -30,6 +30,32 @@ struct RowGeom {
   double pad;
 };
 
+// Cell inverse (row convention: fractional = r inv), determinant and reach_k = r_list / w_k, with
+// w_k = V / |a_{k+1} x a_{k+2}| the perpendicular width, of the cell h (rows are lattice vectors).
+__device__ inline void row_geometry(const double *h, double r_list, RowGeom *g) {
+  const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
+               h22 = h[8];
+  const double det = h00 * (h11 * h22 - h12 * h21) - h01 * (h10 * h22 - h12 * h20) + h02 * (h10 * h21 - h11 * h20);
+  const double id = 1.0 / det;
+  g->inv[0] = (h11 * h22 - h12 * h21) * id;
+  g->inv[1] = (h02 * h21 - h01 * h22) * id;
+  g->inv[2] = (h01 * h12 - h02 * h11) * id;
+  g->inv[3] = (h12 * h20 - h10 * h22) * id;
+  g->inv[4] = (h00 * h22 - h02 * h20) * id;
+  g->inv[5] = (h02 * h10 - h00 * h12) * id;
+  g->inv[6] = (h10 * h21 - h11 * h20) * id;
+  g->inv[7] = (h01 * h20 - h00 * h21) * id;
+  g->inv[8] = (h00 * h11 - h01 * h10) * id;
+  g->det = det;
+  const double vol = fabs(det);
+  const double c0x = h11 * h22 - h12 * h21, c0y = h12 * h20 - h10 * h22, c0z = h10 * h21 - h11 * h20;
+  const double c1x = h21 * h02 - h22 * h01, c1y = h22 * h00 - h20 * h02, c1z = h20 * h01 - h21 * h00;
+  const double c2x = h01 * h12 - h02 * h11, c2y = h02 * h10 - h00 * h12, c2z = h00 * h11 - h01 * h10;
+  g->reach[0] = r_list / (vol / sqrt(c0x * c0x + c0y * c0y + c0z * c0z));
+  g->reach[1] = r_list / (vol / sqrt(c1x * c1x + c1y * c1y + c1z * c1z));
+  g->reach[2] = r_list / (vol / sqrt(c2x * c2x + c2y * c2y + c2z * c2z));
+}
+
 struct StepArgs {
   const int64_t *offs;
   const double *pos_in;  // r_n

@@ -373,10 +373,13 @@ def soft_sphere(api, torch, fire_seconds=60.0, nve_steps=2000, chunk=100):
     time, reported), then NVE at T = 1e-4 (reduced units) from Maxwell-Boltzmann velocities, and
     Langevin at the same temperature."""
     from workloads import maxwell_boltzmann, soft_sphere_jamming_batch
+    from paper_2508_06628_amd.autotune import tune_bin_factor
     w = soft_sphere_jamming_batch(8, 32000, seed=4)
     pot = w.potential
     b = api.Batch.from_workload(w)
     nl = api.build_neighbor_list(b, pot.cutoff, w.skin, bin_factor=2, margin=1.3)
+    bins = tune_bin_factor(b, nl)
+    log(f"soft-sphere bin factor autotune: {bins}")
     pp = api.pair_params_from_spec(pot, w.pair_prec)
     cfg = api.fire_config(**w.extra["fire"])
     fs = api.FireState(b, cfg)
@@ -430,7 +433,8 @@ def soft_sphere(api, torch, fire_seconds=60.0, nve_steps=2000, chunk=100):
     torch.cuda.synchronize()
     lang_ms = e0.elapsed_time(e1)
     _check_list(nl, "soft-sphere Langevin")
-    return dict(workload="soft_sphere_binary_8x32000", n_atoms=b.n_atoms, fire=fire,
+    return dict(workload="soft_sphere_binary_8x32000", n_atoms=b.n_atoms, bin_factor=int(nl.bin_factor),
+                bin_factor_build_ms=bins["ms"], fire=fire,
                 nve=dict(steps=nve_steps, ms_per_step=round(nve_ms / nve_steps, 5),
                          value=round(w.n_atoms * nve_steps / (nve_ms * 1e-3), 1), unit="atom-steps/s",
                          system_rebuilds=int(st[2]), start="FIRE end state" + (" (capped)" if capped else "")),

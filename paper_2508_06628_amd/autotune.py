@@ -10,6 +10,10 @@ returns the fastest; results are cached on disk per (device architecture, potent
 so later runs skip the sweep.  Only timing is done here: every candidate runs the same kernels
 through the C ABI and computes the same trajectory up to float64 summation order.
 
+``tune_bin_factor`` picks the cell-list bin factor b (bins of width at least r_list / b, a stencil
+of (2b + 1)^3 bins) for batches with systems above the LDS limit, the only ones the cell list
+builds: it times forced rebuilds of every row; the rows themselves do not depend on b.
+
 ``tune_fire`` picks how ``ts_fire_step`` runs a relaxation: one persistent launch per call (each
 system on one workgroup, converged systems freeing theirs) or the per-iteration kernels (every
 open system spread over many workgroups), and the lanes per atom of the force kernel.  Batches
@@ -157,4 +161,45 @@ def tune_fire(batch: api.Batch, nl: api.NeighborList, pp, cfg, iters: int = 32, 
         cache[k] = entry
         _store(cache)
     nl.lanes_per_atom = int(lanes)
+    return dict(entry, cached=False)
+
+
+BIN_FACTOR_CHOICES = (1, 2, 3, 4)
+LDS_MAX_ATOMS = 2048  # systems up to this size are rebuilt by the row kernel, without bins
+
+
+def tune_bin_factor(batch: api.Batch, nl: api.NeighborList, reps: int = 3, use_cache: bool = True,
+                    choices=BIN_FACTOR_CHOICES) -> dict:
+    """Pick the cell-list bin factor for ``nl`` on this batch by timing ``reps`` forced rebuilds of a
+    scratch list per candidate.  Batches without a system above 2048 atoms are not binned: the list's
+    factor is kept and nothing is timed.  Returns {"bin_factor": b, "binned": bool, "ms": {...},
+    "cached": bool} and sets the factor on ``nl``."""
+    if batch.max_system_atoms <= LDS_MAX_ATOMS:
+        return {"bin_factor": int(nl.bin_factor), "binned": False, "ms": {}, "cached": False}
+    arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
+    k = f"{arch}/bins/r{nl.cutoff + nl.skin:.4f}/half{int(nl.half)}/{size_bucket(batch, nl)}"
+    cache = _load() if use_cache else {}
+    if k in cache:
+        nl.bin_factor = int(cache[k]["bin_factor"])
+        return dict(cache[k], cached=True)
+    timings = {}
+    for bf in choices:
+        trial = api.NeighborList(batch, nl.cutoff, nl.skin, nl.max_nbr, bf, nl.half, nl.lanes_per_atom,
+                                 nl.group_atoms)
+        api.ts_neighbor_build(batch, trial, force=True)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            api.ts_neighbor_build(batch, trial, force=True)
+        e1.record()
+        torch.cuda.synchronize()
+        timings[bf] = round(e0.elapsed_time(e1) / reps, 4)
+        del trial
+    bf = min(timings, key=timings.get)
+    entry = {"bin_factor": int(bf), "binned": True, "ms": {str(b2): v for b2, v in timings.items()}}
+    if use_cache:
+        cache[k] = entry
+        _store(cache)
+    nl.bin_factor = int(bf)
     return dict(entry, cached=False)

@@ -1,6 +1,8 @@
-"""FIRE autotuner: the choice between the persistent launch and the per-iteration kernels (and the
-lanes per atom) is made on scratch copies, leaves the caller's batch untouched, and the relaxation
-run with the chosen path ends certified by the FP64 oracle (max |F_i| and max |G| below fmax)."""
+"""Autotuners of the FIRE path and of the cell-list bin factor.  FIRE: the choice between the
+persistent launch and the per-iteration kernels (and the lanes per atom) is made on scratch copies,
+leaves the caller's batch untouched, and the relaxation run with the chosen path ends certified by
+the FP64 oracle (max |F_i| and max |G| below fmax).  Bin factor: rows of a binned batch are the
+same for every factor, and the tuner only times batches the cell list builds."""
 import numpy as np
 import pytest
 
@@ -59,3 +61,33 @@ def test_tune_fire_choice_and_certified_relaxation(tmp_path, monkeypatch):
         _, f, Wv = oforces.system_efw(pos[sl], cell[s], w.species[sl], pot.params, pot.kind, pot.cutoff, False)
         assert np.linalg.norm(f, axis=1).max() < fmax * 1.001, s
         assert np.abs(ofire.cell_force(deform[s], Wv, f.shape[0])).max() < fmax * 1.001, s
+
+
+def test_tune_bin_factor_rows_independent_of_the_factor(tmp_path, monkeypatch):
+    """The cell-list bin factor is tuned by timing forced rebuilds; the rows of a binned batch do not
+    depend on it (canonical order), and a batch without systems above 2048 atoms is left alone."""
+    from paper_2508_06628_amd import api
+    from paper_2508_06628_amd.autotune import BIN_FACTOR_CHOICES, tune_bin_factor
+    from workloads import soft_sphere_jamming_batch
+    monkeypatch.setenv("TS_AUTOTUNE_CACHE", str(tmp_path))
+    w = soft_sphere_jamming_batch(2, 2600, seed=23)
+    b = api.Batch.from_workload(w)
+    lists = []
+    for bf in BIN_FACTOR_CHOICES:
+        nl = api.build_neighbor_list(b, w.potential.cutoff, w.skin, bin_factor=bf, margin=1.3)
+        st = nl.read_status()
+        assert st[1] == 0 and st[3] == 0 and st[4] == 0, st
+        lists.append((nl.n_nbr.cpu().numpy(), nl.entries()))
+    for n_nbr, ent in lists[1:]:
+        np.testing.assert_array_equal(n_nbr, lists[0][0])
+        for a, c in zip(ent, lists[0][1]):
+            np.testing.assert_array_equal(a, c)
+    tune = tune_bin_factor(b, nl, reps=2)
+    assert tune["binned"] and tune["bin_factor"] in BIN_FACTOR_CHOICES and nl.bin_factor == tune["bin_factor"]
+    assert len(tune["ms"]) == len(BIN_FACTOR_CHOICES) and not tune["cached"]
+    assert tune_bin_factor(b, nl, reps=2)["cached"]
+    small = copper_uneven_batch(3, seed=95, min_sites=32, max_sites=200)
+    bs = api.Batch.from_workload(small)
+    nls = api.build_neighbor_list(bs, small.potential.cutoff, 0.5, bin_factor=2)
+    t2 = tune_bin_factor(bs, nls)
+    assert not t2["binned"] and t2["bin_factor"] == 2 and nls.bin_factor == 2

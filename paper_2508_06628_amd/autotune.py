@@ -71,11 +71,13 @@ def key(batch, nl, pp) -> str:
     return f"{arch}/kind{pp.kind}/prec{pp.prec}/{size_bucket(batch, nl)}"
 
 
-def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float, steps: int = 50,
-             reps: int = 3, use_cache: bool = True, choices=LANE_CHOICES, rounds=ROUND_CHOICES) -> dict:
-    """Pick lanes_per_atom and group_atoms for ``ts_nve_step`` on this workload.  Returns
-    {"lanes_per_atom": L, "group_atoms": G, "us_per_step": {"L/G": t, ...}, "cached": bool} and sets
-    both on ``nl``."""
+def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float, steps: int = 100,
+             reps: int = 5, use_cache: bool = True, choices=LANE_CHOICES, rounds=ROUND_CHOICES) -> dict:
+    """Pick lanes_per_atom and group_atoms for ``ts_nve_step`` on this workload.  Every candidate
+    runs on its own scratch copy; after a warm-up replay each, the candidates are timed in ``reps``
+    interleaved rounds (so that a clock ramp at the start of a process affects them alike) and each
+    keeps its fastest replay of ``steps`` steps.  Returns {"lanes_per_atom": L, "group_atoms": G,
+    "us_per_step": {"L/G": t, ...}, "cached": bool} and sets both on ``nl``."""
     k = key(batch, nl, pp)
     cache = _load() if use_cache else {}
     if k in cache and "group_atoms" in cache[k]:
@@ -83,8 +85,8 @@ def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float
         nl.group_atoms = int(cache[k]["group_atoms"])
         return dict(cache[k], cached=True)
     prec = "f32" if pp.prec == 0 else "f64"
-    timings = {}
     cands = [(lanes, r * 256 // lanes) for lanes in choices for r in rounds if not (lanes == 1 and r > 1)]
+    trials = []
     for lanes, group in cands:
         b = batch.clone()
         trial = api.NeighborList(b, nl.cutoff, nl.skin, nl.max_nbr, nl.bin_factor, nl.half, lanes, group,
@@ -93,18 +95,20 @@ def tune_nve(batch: api.Batch, nl: api.NeighborList, pp, dt: float, accel: float
         F = api.force_buffer(b, prec)
         api.ts_pair_forces(b, trial, pp, F)
         api.ts_nve_step(b, trial, pp, dt, accel, steps, F, use_graph=True)  # instantiate and warm up
-        torch.cuda.synchronize()
-        best = math.inf
-        for _ in range(reps):
+        trials.append(((lanes, group), b, trial, F))
+    torch.cuda.synchronize()
+    timings = {c: math.inf for c, _, _, _ in trials}
+    for _ in range(reps):
+        for c, b, trial, F in trials:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             api.ts_nve_step(b, trial, pp, dt, accel, steps, F, use_graph=True)
             e1.record()
             torch.cuda.synchronize()
-            best = min(best, e0.elapsed_time(e1) * 1e3 / steps)
-        timings[(lanes, group)] = round(best, 3)
-        del trial, b, F
+            timings[c] = min(timings[c], e0.elapsed_time(e1) * 1e3 / steps)
+    del trials
     api.ts_release_graphs()
+    timings = {c: round(t, 3) for c, t in timings.items()}
     lanes, group = min(timings, key=timings.get)
     entry = {"lanes_per_atom": int(lanes), "group_atoms": int(group),
              "us_per_step": {f"{l2}/{g2}": v for (l2, g2), v in timings.items()}}

@@ -1,8 +1,8 @@
-"""Autotuners of the FIRE path and of the cell-list bin factor.  FIRE: the choice between the
-persistent launch and the per-iteration kernels (and the lanes per atom) is made on scratch copies,
-leaves the caller's batch untouched, and the relaxation run with the chosen path ends certified by
-the FP64 oracle (max |F_i| and max |G| below fmax).  Bin factor: rows of a binned batch are the
-same for every factor, and the tuner only times batches the cell list builds."""
+"""Autotuners.  Step loops: lanes per atom and atoms per workgroup, timed on scratch copies.  FIRE:
+the choice between the persistent launch and the per-iteration kernels (and the lanes per atom) is
+made on scratch copies, leaves the caller's batch untouched, and the relaxation run with the chosen
+path ends certified by the FP64 oracle (max |F_i| and max |G| below fmax).  Bin factor: rows of a
+binned batch are the same for every factor, and the tuner only times batches the cell list builds."""
 import numpy as np
 import pytest
 
@@ -91,3 +91,24 @@ def test_tune_bin_factor_rows_independent_of_the_factor(tmp_path, monkeypatch):
     nls = api.build_neighbor_list(bs, small.potential.cutoff, 0.5, bin_factor=2)
     t2 = tune_bin_factor(bs, nls)
     assert not t2["binned"] and t2["bin_factor"] == 2 and nls.bin_factor == 2
+
+
+def test_tune_nve_choice_cache_and_untouched_batch(tmp_path, monkeypatch):
+    """The step-loop tuner times every (lanes per atom, atoms per workgroup) candidate on scratch
+    copies: the caller's batch is unchanged, the choice is one of the candidates and is cached."""
+    from paper_2508_06628_amd import api
+    from paper_2508_06628_amd.autotune import tune_nve
+    from workloads import argon_batch
+    monkeypatch.setenv("TS_AUTOTUNE_CACHE", str(tmp_path))
+    w = argon_batch(3, seed=41, reps=(3, 3, 3))
+    b = api.Batch.from_workload(w)
+    nl = api.build_neighbor_list(b, w.potential.cutoff, w.skin, bin_factor=2, margin=1.3)
+    pp = api.pair_params_from_spec(w.potential, "f32")
+    pos0, vel0 = b.positions().copy(), b.velocities().copy()
+    t = tune_nve(b, nl, pp, w.dt, w.accel, steps=20, reps=2)
+    assert not t["cached"] and len(t["us_per_step"]) == 7 and all(v > 0 for v in t["us_per_step"].values())
+    assert f"{t['lanes_per_atom']}/{t['group_atoms']}" == min(t["us_per_step"], key=t["us_per_step"].get)
+    assert (nl.lanes_per_atom, nl.group_atoms) == (t["lanes_per_atom"], t["group_atoms"])
+    np.testing.assert_array_equal(b.positions(), pos0)
+    np.testing.assert_array_equal(b.velocities(), vel0)
+    assert tune_nve(b, nl, pp, w.dt, w.accel, steps=20, reps=2)["cached"]

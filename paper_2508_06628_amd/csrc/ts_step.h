@@ -27,11 +27,12 @@ struct RowGeom {
   double inv[9];
   double reach[3];
   double det;
-  double pad;
+  double bound;  // r_list + delta, the distance bound of the float32 prefilters of a rebuild
 };
 
-// Cell inverse (row convention: fractional = r inv), determinant and reach_k = r_list / w_k, with
-// w_k = V / |a_{k+1} x a_{k+2}| the perpendicular width, of the cell h (rows are lattice vectors).
+// Cell inverse (row convention: fractional = r inv), determinant, reach_k = r_list / w_k, with
+// w_k = V / |a_{k+1} x a_{k+2}| the perpendicular width, and the prefilter bound of the cell h
+// (rows are lattice vectors).
 __device__ inline void row_geometry(const double *h, double r_list, RowGeom *g) {
   const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                h22 = h[8];
@@ -54,6 +55,11 @@ __device__ inline void row_geometry(const double *h, double r_list, RowGeom *g) 
   g->reach[0] = r_list / (vol / sqrt(c0x * c0x + c0y * c0y + c0z * c0z));
   g->reach[1] = r_list / (vol / sqrt(c1x * c1x + c1y * c1y + c1z * c1z));
   g->reach[2] = r_list / (vol / sqrt(c2x * c2x + c2y * c2y + c2z * c2z));
+  // delta bounds the float32 rounding of wrapped fractional coordinates and of the distances built
+  // from them (a few 1e-5 A at most) with a wide margin
+  const double rowsum = sqrt(h00 * h00 + h01 * h01 + h02 * h02) + sqrt(h10 * h10 + h11 * h11 + h12 * h12) +
+                        sqrt(h20 * h20 + h21 * h21 + h22 * h22);
+  g->bound = r_list + 1e-4 + 4e-6 * rowsum;
 }
 
 struct StepArgs {

@@ -534,11 +534,6 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
     //    the other two lattice vectors); pass 1 keeps candidates with max_k |d_k| w_k below the
     //    bound and pass 2 enumerates every image within reach;
     //  * other cells, small systems: every candidate takes pass 2.
-    auto bound = [&]() {  // r_list + delta
-      const double rowsum = sqrt(h00 * h00 + h01 * h01 + h02 * h02) + sqrt(h10 * h10 + h11 * h11 + h12 * h12) +
-                            sqrt(h20 * h20 + h21 * h21 + h22 * h22);
-      return a.r_list + 1e-4 + 4e-6 * rowsum;
-    };
     int pend = 0;
     // queue the survivors of two blocks of 64 candidates per iteration (independent chains until
     // their ballots); the queue holds up to 3 x 64 survivors, and every full 64 of them take pass 2
@@ -570,7 +565,7 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
     };
     if (wide) {
       const float4 fi = sf[li];
-      const double rc = bound();
+      const double rc = geo.bound;
       const float g00 = (float)h00, g01 = (float)h01, g02 = (float)h02, g10 = (float)h10, g11 = (float)h11,
                   g12 = (float)h12, g20 = (float)h20, g21 = (float)h21, g22 = (float)h22;
       const float rc2f = (float)(rc * rc);
@@ -706,7 +701,7 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
       };
       if constexpr (COMPACT) {
         const float4 fi = sf[li];
-        const double rc = bound();
+        const double rc = geo.bound;
         // perpendicular widths w_k = r_list / reach_k
         const float w0 = (float)(a.r_list / re0), w1 = (float)(a.r_list / re1), w2 = (float)(a.r_list / re2);
         const float rcf = (float)rc;

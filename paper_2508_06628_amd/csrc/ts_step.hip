@@ -597,18 +597,23 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
         if (in && p < a.max_nbr) nbr[row_index(p, i, st)] = pack_entry(j, s0, s1, s2);
         cnt += __popcll(m);
       };
-      auto near_f32 = [&](int j) {  // float32 nearest-image test of candidate j (false past the end)
+      // float32 nearest-image test of candidate j (false past the end); DIAG: a cell whose
+      // off-diagonal entries are zero, where the pair vector needs one product per component
+      auto near_f32 = [&](int j, auto diag_c) {
+        constexpr bool DIAG = decltype(diag_c)::value;
         const float4 fj = sf[j < ns ? j : li];
         float dfx = fj.x - fi.x, dfy = fj.y - fi.y, dfz = fj.z - fi.z;
         dfx -= rintf(dfx);
         dfy -= rintf(dfy);
         dfz -= rintf(dfz);
-        const float dx = dfx * g00 + dfy * g10 + dfz * g20;
-        const float dy = dfx * g01 + dfy * g11 + dfz * g21;
-        const float dz = dfx * g02 + dfy * g12 + dfz * g22;
+        const float dx = DIAG ? dfx * g00 : dfx * g00 + dfy * g10 + dfz * g20;
+        const float dy = DIAG ? dfy * g11 : dfx * g01 + dfy * g11 + dfz * g21;
+        const float dz = DIAG ? dfz * g22 : dfx * g02 + dfy * g12 + dfz * g22;
         return (j < ns) & (dx * dx + dy * dy + dz * dz < rc2f);
       };
-      scan(near_f32, exact);
+      const bool diag = h01 == 0.0 && h02 == 0.0 && h10 == 0.0 && h12 == 0.0 && h20 == 0.0 && h21 == 0.0;
+      if (diag) scan([&](int j) { return near_f32(j, std::true_type{}); }, exact);
+      else scan([&](int j) { return near_f32(j, std::false_type{}); }, exact);
     } else {
       // every image within r_list of candidate j (one per lane, valid lanes only), compacted into
       // the row in (lane, S0, S1, S2) order

@@ -449,8 +449,9 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
       if (threadIdx.x < 9) a.ref_cell[9 * (int64_t)s + threadIdx.x] = h[threadIdx.x];
       if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.status[TS_STATUS_REBUILDS], 1ull);
     }
-    // cell, inverse and reach: from the step loop's per-call table, else uniform values every lane
-    // computes itself (no serial section); both come from row_geometry
+    // cell, inverse, reach and prefilter bound: from the per-system table (computed once per call by
+    // the step loops, per update by the list-init kernel), else uniform values every lane computes
+    // itself (no serial section); both come from row_geometry
     const double h00 = h[0], h01 = h[1], h02 = h[2], h10 = h[3], h11 = h[4], h12 = h[5], h20 = h[6], h21 = h[7],
                  h22 = h[8];
     RowGeom geo;
@@ -474,8 +475,7 @@ __device__ void rebuild_rows(const StepArgs &a, int wg, int n_wg, int chunks1, c
     constexpr bool lds_pos = !kCompact;
     double *lx = lds, *ly = lds + ns, *lz = lds + 2 * ns;
     float4 *sf = reinterpret_cast<float4 *>(kCompact ? lds : lds + 3 * ns + (ns & 1));
-    int *surv = reinterpret_cast<int *>(kCompact ? lds + 3 * ns : reinterpret_cast<double *>(sf + ns)) +
-                wave * kSurvCap;
+    int *surv = reinterpret_cast<int *>(sf + ns) + wave * kSurvCap;
     const double *__restrict__ gx = pin + a0, *__restrict__ gy = pin + a.st_in + a0, *__restrict__ gz =
                                                                                        pin + 2 * a.st_in + a0;
     {
@@ -755,14 +755,14 @@ __global__ void __launch_bounds__(kWave * kRebuildWaves) k_rebuild_rows(StepArgs
 
 int launch_rebuild(const StepArgs &a, int64_t n_sys, int64_t max_atoms, hipStream_t st) {
   // float64 positions, float4 fractional coordinates (after one alignment double) and the
-  // survivor queues (wide cells); beyond kRebuildFullLds, the compact layout (float64 positions of
-  // cells that are not wide, else the fractional coordinates alone)
+  // survivor queues; beyond kRebuildFullLds, the compact layout (the fractional coordinates and the
+  // queues)
   const size_t queues = sizeof(int) * kSurvCap * kRebuildWaves;
   const size_t full = (size_t)(5 * max_atoms + 1) * sizeof(double) + queues;
   StepArgs b = a;
   b.n_sys = (int)n_sys;
   const bool compact = full > kRebuildFullLds;
-  const size_t shm = compact ? (size_t)3 * max_atoms * sizeof(double) + queues : full;
+  const size_t shm = compact ? (size_t)max_atoms * sizeof(float4) + queues : full;
   // one workgroup per chunk up to what the CUs hold at once (every workgroup then loops over chunks
   // from the start, none waits for a free slot)
   const int chunks1 = (int)ceil_div(max_atoms, kRebuildWaves);

@@ -176,16 +176,19 @@ def alu_roofline(summary: str, kernel: str, avg_us: float):
                 valu_insts_per_launch=n)
 
 
+ROOFLINE_LANES, ROOFLINE_GROUP = 2, 128
+
+
 def force_kernel_roofline(api, torch, r, reps=200):
     """Average duration of the pair-force kernel alone, timed with events on the stream it is
     launched on (torch's current stream), and its algorithmic HBM bytes.  For systems that fit the
     LDS (up to 2048 atoms) the force entry point runs the step kernel in its forces-only mode: one
     workgroup per system, positions staged in LDS."""
     b, nl, pp, F = r["batch"], r["nl"], r["pp"], r["F"]
-    # four lanes per atom, the configuration of the committed counter summaries (the step loop
-    # keeps the autotuner's choice)
+    # two lanes per atom and 128 atoms per workgroup: the autotuner's choice on this batch and the
+    # configuration of the committed counter summaries (the step loop keeps the autotuner's choice)
     tuned = nl.lanes_per_atom, nl.group_atoms
-    nl.lanes_per_atom, nl.group_atoms = 4, 0
+    nl.lanes_per_atom, nl.group_atoms = ROOFLINE_LANES, ROOFLINE_GROUP
     stream = torch.cuda.current_stream()
     for _ in range(10):
         api.ts_pair_forces(b, nl, pp, F, stream=stream)
@@ -205,9 +208,8 @@ def force_kernel_roofline(api, torch, r, reps=200):
     # per system: atom offset 8 B and cell 72 B
     alg = n * (24 + 4 + 3 * fbytes) + 4 * entries + n_sys * (8 + 72)
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    tl = 4
     ftype = "float" if fbytes == 4 else "double"
-    kernel = f"ts::k_step<0, {ftype}, {tl}, 3>"
+    kernel = f"ts::k_step<0, {ftype}, {ROOFLINE_LANES}, 3>"
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_counter("k_step_argon_64x864_counters.txt", "traffic_bytes_per_launch",

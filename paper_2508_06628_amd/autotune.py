@@ -128,11 +128,13 @@ def tuned_lanes(batch, nl, pp) -> Optional[int]:
 FIRE_LANE_CHOICES = (2, 4)
 
 
-def tune_fire(batch: api.Batch, nl: api.NeighborList, pp, cfg, iters: int = 32, use_cache: bool = True,
-              choices=FIRE_LANE_CHOICES) -> dict:
+def tune_fire(batch: api.Batch, nl: api.NeighborList, pp, cfg, iters: int = 32, reps: int = 2,
+              use_cache: bool = True, choices=FIRE_LANE_CHOICES) -> dict:
     """Pick the FIRE path (persistent launch or per-iteration kernels) and lanes_per_atom for
     ``ts_fire_step`` on this workload.  Each candidate relaxes a scratch copy of the batch from a
-    fresh FIRE state for ``iters`` iterations (after two warm-up iterations).  Returns
+    fresh FIRE state: two warm-up iterations, then ``reps`` rounds of ``iters`` iterations, the
+    candidates interleaved within each round; a candidate's time is the sum of its rounds (the
+    relaxation advances, so every candidate covers the same iterations).  Returns
     {"persistent": P, "lanes_per_atom": L, "ms": {"P/L": t, ...}, "cached": bool} and sets the lanes
     on ``nl``."""
     k = f"fire/{key(batch, nl, pp)}/cell{int(cfg.relax_cell)}"
@@ -141,7 +143,7 @@ def tune_fire(batch: api.Batch, nl: api.NeighborList, pp, cfg, iters: int = 32, 
         nl.lanes_per_atom = int(cache[k]["lanes_per_atom"])
         return dict(cache[k], cached=True)
     prec = "f32" if pp.prec == 0 else "f64"
-    timings = {}
+    trials = []
     for persistent in (True, False):
         for lanes in choices:
             b = batch.clone()
@@ -150,14 +152,19 @@ def tune_fire(batch: api.Batch, nl: api.NeighborList, pp, cfg, iters: int = 32, 
             fs = api.FireState(b, cfg)
             F = api.force_buffer(b, prec)
             api.ts_fire_step(b, fs, cfg, trial, pp, 2, F, persistent=persistent)
-            torch.cuda.synchronize()
+            trials.append(((persistent, lanes), b, trial, fs, F))
+    torch.cuda.synchronize()
+    timings = {c: 0.0 for c, *_ in trials}
+    for _ in range(reps):
+        for c, b, trial, fs, F in trials:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            api.ts_fire_step(b, fs, cfg, trial, pp, iters, F, persistent=persistent)
+            api.ts_fire_step(b, fs, cfg, trial, pp, iters, F, persistent=c[0])
             e1.record()
             torch.cuda.synchronize()
-            timings[(persistent, lanes)] = round(e0.elapsed_time(e1), 3)
-            del trial, b, F, fs
+            timings[c] += e0.elapsed_time(e1)
+    del trials
+    timings = {c: round(t, 3) for c, t in timings.items()}
     persistent, lanes = min(timings, key=timings.get)
     entry = {"persistent": bool(persistent), "lanes_per_atom": int(lanes),
              "ms": {f"{int(p2)}/{l2}": v for (p2, l2), v in timings.items()}}
